@@ -1,0 +1,194 @@
+/*
+ * bfx.h -- C ABI of an MI355X (gfx950) FX-correlator hot path.
+ *
+ * The calls follow the gulp model of the Bifrost paper (Sec. 3.1: a block
+ * reads a ring buffer one "gulp" at a time; the ring defaults to four gulps):
+ * each call consumes one gulp that already sits in caller-owned device memory
+ * and enqueues its work on the caller's HIP stream.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Ownership: the caller owns every device buffer.  accumulate / dump /
+ *   fengine / beamform never allocate or free device memory.  A plan owns
+ *   host metadata only, except a batched plan, which also owns a small device
+ *   work list (allocated by bfx_xengine_create_batched, freed by destroy).
+ * - Asynchrony: calls enqueue on `stream` (a hipStream_t; NULL = the null
+ *   stream) and return.  Argument errors are detected on the host and
+ *   returned before anything is enqueued; a failing HIP launch is reported as
+ *   BFX_EHIP.  Device-side faults surface at the caller's next synchronisation.
+ * - Threads: a plan may be used by one thread at a time; different plans are
+ *   independent.  Error details are kept per thread (bfx_last_error_detail).
+ * - Layouts are fixed (no layout flags):
+ *     voltages   [time][channel][input], time slowest, input fastest;
+ *                input = 2*antenna + polarisation;
+ *     ci8        two int8 per sample, real byte first (Sec. 6: "8+8");
+ *     ci4        one byte per sample, real part in bits 7..4, imaginary part
+ *                in bits 3..0, each 4-bit two's complement (Sec. 6: "4+4"
+ *                complex signed integers; the nibble order is this library's
+ *                convention -- the paper does not state one);
+ *     cf16       two IEEE binary16 per sample, real first;
+ *     visibility [channel][p][2] with p = i*(i+1)/2 + j, j <= i (row-major
+ *                lower triangle including the autocorrelations), the pair
+ *                (re, im) of V_ij = sum_t x_i(t) * conj(x_j(t)).
+ */
+#ifndef BFX_H
+#define BFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bfx_status {
+    BFX_OK = 0,
+    BFX_EINVAL = -1,  /* bad argument: null/misaligned pointer, bad size, dtype */
+    BFX_ERANGE = -2,  /* integration would overflow the int32 accumulator     */
+    BFX_EHIP = -3,    /* a HIP runtime call failed (detail has hipGetErrorString) */
+    BFX_ENOTSUP = -4, /* valid request this build does not implement         */
+    BFX_ENOMEM = -5   /* host or device allocation at plan creation failed   */
+} bfx_status;
+
+typedef enum bfx_dtype {
+    BFX_I8 = 1,   /* real int8 (F-engine input)               */
+    BFX_CI4 = 2,  /* 4+4-bit complex, see layout above         */
+    BFX_CI8 = 3,  /* 8+8-bit complex                           */
+    BFX_CF16 = 4, /* binary16 complex                          */
+    BFX_CF32 = 5, /* binary32 complex                          */
+    BFX_CI32 = 6, /* int32 complex (integer visibilities)      */
+    BFX_CF64 = 7  /* binary64 complex (running sums)           */
+} bfx_dtype;
+
+/* hipStream_t, passed as a plain pointer so that this header needs no HIP
+ * include.  NULL selects the null stream.                                   */
+typedef void *bfx_stream;
+
+/* Flag for bfx_xengine_accumulate: write V instead of adding to d_acc. */
+#define BFX_ACC_OVERWRITE 1u
+
+typedef struct bfx_xengine bfx_xengine; /* opaque plan */
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *bfx_strerror(bfx_status s);
+
+/* Detail of the last error raised on the calling thread ("" if none).
+ * Valid until the next bfx_* call on this thread.                          */
+const char *bfx_last_error_detail(void);
+
+/* ------------------------------------------------------------------------ */
+/* X-engine (Sec. 2.2 linear-algebra module; Sec. 7 lists correlation as the
+ * capability being added).  Per channel f it forms the Hermitian visibility
+ * matrix V_f = sum_t x_t x_t^H over the time samples of a gulp, keeping the
+ * lower triangle only.
+ *
+ * Input dtypes and results:
+ *   BFX_CI4, BFX_CI8 -> int32 visibilities, bit-exact (int8 MFMA, int32
+ *                       accumulation; the sums are exact integers);
+ *   BFX_CF16         -> binary32 visibilities (FP16 MFMA, FP32 accumulation).
+ */
+
+/* Largest number of samples one integration (the samples accumulated since the
+ * last BFX_ACC_OVERWRITE) may hold before an int32 visibility could overflow:
+ *   ci8: floor((2^31-1) / (2*128^2)) = 65535
+ *   ci4: floor((2^31-1) / (2*8^2))   = 16777215
+ *   cf16: INT64_MAX (no integer bound).
+ * Returns -1 for any other dtype.                                           */
+int64_t bfx_xengine_max_ntime(bfx_dtype in);
+
+/* Create a plan for one array of `ninput` inputs and `nchan` channels.
+ * ninput must be a positive multiple of 4 (<= 8192), nchan positive
+ * (<= 65536), `in` one of BFX_CI4, BFX_CI8, BFX_CF16.  Host-only: no device
+ * memory is allocated.  On success *plan receives the new plan.            */
+bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan, bfx_dtype in);
+
+/* Create a batched plan: `nsub` independent arrays (subarrays / subbands) of
+ * ninput[k] inputs and nchan[k] channels, correlated by one launch.  Inputs
+ * and outputs live in two arenas; bfx_xengine_sub_offsets gives where each
+ * subarray's gulp and visibilities start.  Allocates a device work list on
+ * the current device (BFX_ENOMEM / BFX_EHIP on failure).                    */
+bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const int32_t *ninput,
+                                      const int32_t *nchan, bfx_dtype in);
+
+/* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
+ * destroy a batched plan while work enqueued with it is still running.      */
+bfx_status bfx_xengine_destroy(bfx_xengine *plan);
+
+/* Bytes of one input gulp of `ntime` samples, and bytes of the visibility
+ * buffer (the accumulator; int32 pairs or binary32 pairs).  For batched plans
+ * these are arena sizes.  Return 0 on a bad argument.                       */
+size_t bfx_xengine_in_bytes(const bfx_xengine *plan, int64_t ntime);
+size_t bfx_xengine_out_bytes(const bfx_xengine *plan);
+
+/* Subarray k of a batched plan (k = 0 for a plain plan): byte offset of its
+ * [ntime][nchan_k][ninput_k] gulp inside the input arena, and byte offset of
+ * its [nchan_k][p][2] visibilities inside the output arena.  Every offset is a
+ * multiple of 256.                                                          */
+bfx_status bfx_xengine_sub_offsets(const bfx_xengine *plan, int32_t k, int64_t ntime,
+                                   int64_t *in_offset, int64_t *out_offset);
+
+/* Samples accumulated since the last BFX_ACC_OVERWRITE (host bookkeeping). */
+int64_t bfx_xengine_nacc(const bfx_xengine *plan);
+
+/* Correlate one gulp.
+ *   d_in   device, [ntime][nchan][ninput] samples of the plan's dtype (for a
+ *          batched plan: the input arena), 16-byte aligned;
+ *   ntime  samples in the gulp, >= 1;
+ *   d_acc  device, the visibility buffer (bfx_xengine_out_bytes), 16-byte
+ *          aligned; with BFX_ACC_OVERWRITE it is overwritten with this gulp's
+ *          V, otherwise V is added to it.
+ * Returns BFX_ERANGE, without enqueueing, when the integer bound
+ * bfx_xengine_max_ntime would be exceeded by nacc + ntime.  Results do not
+ * depend on launch shape or scheduling (integer sums are exact).            */
+bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t ntime, void *d_acc,
+                                  uint32_t flags, bfx_stream stream);
+
+/* Hand over an integration (Sec. 4.1 accumulate block).
+ *   d_acc    device visibility buffer filled by accumulate;
+ *   d_out    device, may be NULL or == d_acc (no copy); otherwise the
+ *            visibilities are copied there (same dtype and size);
+ *   d_run64  device, may be NULL; otherwise [nchan][p][2] binary64 running
+ *            sum, updated as d_run64 += (double)d_acc.
+ * Does not change nacc: start the next integration with BFX_ACC_OVERWRITE.  */
+bfx_status bfx_xengine_dump(bfx_xengine *plan, const void *d_acc, void *d_out, double *d_run64,
+                            bfx_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* F-engine (Sec. 2.2 FFT and quantize modules; Sec. 6: 204.8 MS/s real
+ * samples become 4096 channels, i.e. a real transform of 2N points keeps the
+ * N channels below Nyquist).
+ *   d_in     device int8 [nspec*nfft][ninput]: real samples, inputs fastest;
+ *   nfft     transform length, a power of two in [64, 8192];
+ *   ninput   positive, even;
+ *   nspec    number of non-overlapping frames per input (rectangular window);
+ *   d_scale  device float[nfft/2], per-channel requantization scale (ignored
+ *            for BFX_CF32 output);
+ *   d_out    device [nspec][nfft/2][ninput] of `out`:
+ *              BFX_CI8:  q = clamp(round_half_even(scale_k * X), -127, 127)
+ *                        for the real and imaginary parts separately;
+ *              BFX_CF32: the unscaled spectrum X in binary32.
+ * X_s[k][i] = sum_{n<nfft} x[s*nfft+n][i] exp(-2 pi i k n / nfft),
+ * k = 0 .. nfft/2-1 (bin 0 = DC, Nyquist dropped, no normalisation).
+ * Computed in binary32.  The ci8 output can be fed straight to an X-engine
+ * plan with ninput inputs and nfft/2 channels.                              */
+bfx_status bfx_fengine(const int8_t *d_in, int32_t ninput, int32_t nfft, int64_t nspec,
+                       const float *d_scale, void *d_out, bfx_dtype out, bfx_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Phase-and-sum beamformer with square-law detection and integration (Sec. 6
+ * DRX pipeline; Sec. 4.1 detect and accumulate blocks).
+ *   d_x    device cf16 [ntime][nchan][ninput];
+ *   d_w    device cf16 [nchan][nbeam][ninput] steering weights, applied
+ *          without conjugation: y[b][f][t] = sum_i w[f][b][i] * x[t][f][i];
+ *   d_out  device float [nbeam][nchan][ntime/navg]:
+ *          P[b][f][u] = sum_{t=u*navg}^{u*navg+navg-1} |y[b][f][t]|^2.
+ * ntime must be a positive multiple of navg; ninput a positive multiple of
+ * 32; nbeam in [1, 256].  FP16 products, FP32 accumulation.                 */
+bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput, int32_t nchan,
+                               int32_t nbeam, int64_t ntime, int32_t navg, float *d_out,
+                               bfx_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFX_H */

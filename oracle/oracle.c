@@ -1,0 +1,311 @@
+/*
+ * oracle.c -- plain, slow CPU reference for the FX-correlator hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * with the GPU path.
+ *
+ * Everything here is the textbook definition written out as loops, in int64
+ * for integer data and in double precision for floating point:
+ *
+ *   - unpack of 4+4-bit and 8+8-bit complex signed integers
+ *     (paper Sec. 6, packet capture and TBN pipeline: voltages travel as
+ *      "4+4" complex signed integers and are unpacked to "8+8");
+ *   - the X-engine product V_f = sum_t x_t x_t^H per channel
+ *     (paper Sec. 2.2 linear-algebra module; Sec. 7 lists correlation as the
+ *      capability being built; the product itself is the standard FX
+ *      correlator definition V_ij = sum_t x_i(t) conj(x_j(t)));
+ *   - a direct DFT of real frames (paper Sec. 2.2 FFT module; Sec. 6: the
+ *     F-engine turns 204.8 MS/s into 4096 channels, i.e. a real transform of
+ *     2N points keeps N channels);
+ *   - requantization to 8-bit (paper Sec. 2.2 quantize module; Sec. 4.1
+ *     quantize block);
+ *   - phase-and-sum beamforming with square-law detection and integration
+ *     (paper Sec. 6 DRX pipeline; Sec. 4.1 detect and accumulate blocks).
+ *
+ * Where the paper is silent, the reading taken is written next to the code.
+ * Optional OpenMP over the outermost (channel / spectrum) loop does not change
+ * any arithmetic: every output element is computed by exactly one thread in the
+ * same order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Unpack.  Reading: one byte per 4+4 sample, real part in the high nibble,
+ * imaginary part in the low nibble, each a 4-bit two's-complement integer.
+ * 8+8 samples are two int8 bytes, real first.                               */
+
+static int nibble_value(int nib)
+{
+    int v = nib & 15;
+    if (v >= 8) v -= 16;
+    return v;
+}
+
+int orc_unpack_ci4(const uint8_t *in, int64_t n, int32_t *re, int32_t *im)
+{
+    if (!in || !re || !im || n < 0) return ORC_EINVAL;
+    for (int64_t k = 0; k < n; ++k) {
+        int b = in[k];
+        re[k] = nibble_value(b >> 4);
+        im[k] = nibble_value(b);
+    }
+    return ORC_OK;
+}
+
+int orc_unpack_ci8(const int8_t *in, int64_t n, int32_t *re, int32_t *im)
+{
+    if (!in || !re || !im || n < 0) return ORC_EINVAL;
+    for (int64_t k = 0; k < n; ++k) {
+        re[k] = in[2 * k];
+        im[k] = in[2 * k + 1];
+    }
+    return ORC_OK;
+}
+
+/* Read sample (t, f, i) of a [t][f][i] voltage array.  dtype 4 = ci4 (one
+ * byte per sample), dtype 8 = ci8 (two bytes per sample).                    */
+static void sample_at(const void *in, int dtype, int64_t t, int32_t nchan,
+                      int32_t ninput, int32_t f, int32_t i, int64_t *re, int64_t *im)
+{
+    int64_t idx = (t * nchan + f) * (int64_t)ninput + i;
+    if (dtype == 4) {
+        int b = ((const uint8_t *)in)[idx];
+        *re = nibble_value(b >> 4);
+        *im = nibble_value(b);
+    } else {
+        const int8_t *p = (const int8_t *)in;
+        *re = p[2 * idx];
+        *im = p[2 * idx + 1];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integer X-engine.  For channels f0..f0+nf-1 and time samples t0..t0+nt-1:
+ *
+ *   V_ij = sum_t x_i(t) * conj(x_j(t))
+ *   Re V_ij = sum_t re_i re_j + im_i im_j
+ *   Im V_ij = sum_t im_i re_j - re_i im_j
+ *
+ * full == 0: lower triangle j <= i, packed row-major, p = i(i+1)/2 + j,
+ *            out is [nf][N(N+1)/2][2] int64.
+ * full != 0: every (i, j), out is [nf][N][N][2] int64.                      */
+int orc_xengine_int(const void *in, int dtype, int64_t ntime, int32_t nchan,
+                    int32_t ninput, int32_t f0, int32_t nf, int64_t t0, int64_t nt,
+                    int full, int64_t *out, int nthreads)
+{
+    if (!in || !out || (dtype != 4 && dtype != 8)) return ORC_EINVAL;
+    if (ntime < 0 || nchan <= 0 || ninput <= 0) return ORC_EINVAL;
+    if (f0 < 0 || nf < 0 || f0 + nf > nchan) return ORC_EINVAL;
+    if (t0 < 0 || nt < 0 || t0 + nt > ntime) return ORC_EINVAL;
+    const int64_t N = ninput;
+    const int64_t per_chan = full ? N * N : N * (N + 1) / 2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int32_t ff = 0; ff < nf; ++ff) {
+        int32_t f = f0 + ff;
+        int64_t *o = out + (int64_t)ff * per_chan * 2;
+        for (int64_t i = 0; i < N; ++i) {
+            int64_t jmax = full ? N - 1 : i;
+            for (int64_t j = 0; j <= jmax; ++j) {
+                int64_t acc_re = 0, acc_im = 0;
+                for (int64_t t = t0; t < t0 + nt; ++t) {
+                    int64_t ar, ai, br, bi;
+                    sample_at(in, dtype, t, nchan, ninput, f, (int32_t)i, &ar, &ai);
+                    sample_at(in, dtype, t, nchan, ninput, f, (int32_t)j, &br, &bi);
+                    acc_re += ar * br + ai * bi;
+                    acc_im += ai * br - ar * bi;
+                }
+                int64_t p = full ? i * N + j : i * (i + 1) / 2 + j;
+                o[2 * p] = acc_re;
+                o[2 * p + 1] = acc_im;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* The same product on decoded double-precision voltages (used for the FP16
+ * X-engine: every FP16 value is exact in double, so this is the exact sum up
+ * to double rounding).  re/im are [nt][nf][N]; out is [nf][P][2] double.     */
+int orc_xengine_f64(const double *re, const double *im, int64_t nt, int32_t nf,
+                    int32_t ninput, int full, double *out, int nthreads)
+{
+    if (!re || !im || !out || nt < 0 || nf <= 0 || ninput <= 0) return ORC_EINVAL;
+    const int64_t N = ninput;
+    const int64_t per_chan = full ? N * N : N * (N + 1) / 2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int32_t f = 0; f < nf; ++f) {
+        double *o = out + (int64_t)f * per_chan * 2;
+        for (int64_t i = 0; i < N; ++i) {
+            int64_t jmax = full ? N - 1 : i;
+            for (int64_t j = 0; j <= jmax; ++j) {
+                double acc_re = 0.0, acc_im = 0.0;
+                for (int64_t t = 0; t < nt; ++t) {
+                    int64_t a = (t * nf + f) * N + i;
+                    int64_t b = (t * nf + f) * N + j;
+                    acc_re += re[a] * re[b] + im[a] * im[b];
+                    acc_im += im[a] * re[b] - re[a] * im[b];
+                }
+                int64_t p = full ? i * N + j : i * (i + 1) / 2 + j;
+                o[2 * p] = acc_re;
+                o[2 * p + 1] = acc_im;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Running sum of dumps: run[k] += dump[k] in double (integration across
+ * dumps, paper Sec. 4.1 accumulate block).                                  */
+int orc_accumulate_f64(double *run, const double *dump, int64_t n)
+{
+    if (!run || !dump || n < 0) return ORC_EINVAL;
+    for (int64_t k = 0; k < n; ++k) run[k] += dump[k];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct DFT of real frames.  x is [nspec*nfft][ninput] int8 (time-major,
+ * inputs innermost).  Frame s of input i is x[s*nfft + n][i], n < nfft.
+ *
+ *   X_s[k][i] = sum_n x[s*nfft+n][i] * exp(-2 pi i k n / nfft),
+ *   k = 0 .. nfft/2 - 1 (the Nyquist bin is dropped; bin 0 is DC),
+ *   forward sign, no normalisation, rectangular window, no overlap.
+ *
+ * Twiddles come from a double table indexed by the exact integer (k*n) mod
+ * nfft, so no phase error accumulates with n.  out is
+ * [nspec][nfft/2][ninput][2] double.                                        */
+int orc_dft_real(const int8_t *x, int32_t ninput, int32_t nfft, int64_t nspec,
+                 double *out, int nthreads)
+{
+    if (!x || !out || ninput <= 0 || nfft <= 1 || (nfft & 1) || nspec < 0)
+        return ORC_EINVAL;
+    double *c = (double *)malloc(sizeof(double) * (size_t)nfft);
+    double *s = (double *)malloc(sizeof(double) * (size_t)nfft);
+    if (!c || !s) { free(c); free(s); return ORC_EINVAL; }
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int32_t m = 0; m < nfft; ++m) {
+        c[m] = cos(two_pi * (double)m / (double)nfft);
+        s[m] = sin(two_pi * (double)m / (double)nfft);
+    }
+    const int32_t nchan = nfft / 2;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t sp = 0; sp < nspec; ++sp) {
+        for (int32_t k = 0; k < nchan; ++k) {
+            for (int32_t i = 0; i < ninput; ++i) {
+                double acc_re = 0.0, acc_im = 0.0;
+                for (int32_t n = 0; n < nfft; ++n) {
+                    double v = (double)x[(sp * nfft + n) * (int64_t)ninput + i];
+                    int64_t m = ((int64_t)k * n) % nfft;
+                    acc_re += v * c[m];
+                    acc_im -= v * s[m];
+                }
+                int64_t o = ((sp * nchan + k) * (int64_t)ninput + i) * 2;
+                out[o] = acc_re;
+                out[o + 1] = acc_im;
+            }
+        }
+    }
+    free(c);
+    free(s);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Requantize to 8+8.  Reading: a caller-supplied per-channel scale, round half
+ * to even, saturate to the symmetric range [-127, 127] (so -128 is never
+ * produced).  The rounding decision is taken in single precision, as the
+ * kernel takes it: q = sat(rint_even(fl32(scale * fl32(v)))).
+ * X is [nspec][nchan][ninput][2] double, out is [nspec][nchan][ninput][2] int8. */
+static int8_t requant_one(double v, float scale)
+{
+    float prod = scale * (float)v;
+    float r = rintf(prod); /* default rounding mode: half to even */
+    if (r > 127.0f) r = 127.0f;
+    if (r < -127.0f) r = -127.0f;
+    if (r != r) r = 0.0f; /* NaN never arises from finite input */
+    return (int8_t)r;
+}
+
+int orc_requantize(const double *X, const float *scale, int64_t nspec, int32_t nchan,
+                   int32_t ninput, int8_t *out)
+{
+    if (!X || !scale || !out || nspec < 0 || nchan <= 0 || ninput <= 0) return ORC_EINVAL;
+    for (int64_t sp = 0; sp < nspec; ++sp)
+        for (int32_t k = 0; k < nchan; ++k)
+            for (int32_t i = 0; i < ninput; ++i) {
+                int64_t o = ((sp * nchan + k) * (int64_t)ninput + i) * 2;
+                out[o] = requant_one(X[o], scale[k]);
+                out[o + 1] = requant_one(X[o + 1], scale[k]);
+            }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase-and-sum beamformer with square-law detection and integration.
+ *
+ *   y[b][f][t]  = sum_i w[f][b][i] * x[t][f][i]          (no conjugation)
+ *   P[b][f][u]  = sum_{t = u*navg}^{u*navg+navg-1} |y[b][f][t]|^2
+ *
+ * xre/xim are [ntime][nchan][ninput], wre/wim [nchan][nbeam][ninput] (decoded
+ * FP16 values, exact in double); out is [nbeam][nchan][ntime/navg] double.   */
+int orc_beamform_detect(const double *xre, const double *xim, const double *wre,
+                        const double *wim, int64_t ntime, int32_t nchan, int32_t ninput,
+                        int32_t nbeam, int32_t navg, double *out, int nthreads)
+{
+    if (!xre || !xim || !wre || !wim || !out) return ORC_EINVAL;
+    if (ntime < 0 || nchan <= 0 || ninput <= 0 || nbeam <= 0 || navg <= 0) return ORC_EINVAL;
+    if (ntime % navg) return ORC_EINVAL;
+    const int64_t nout = ntime / navg;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int32_t f = 0; f < nchan; ++f) {
+        for (int32_t b = 0; b < nbeam; ++b) {
+            for (int64_t u = 0; u < nout; ++u) {
+                double power = 0.0;
+                for (int64_t t = u * navg; t < (u + 1) * navg; ++t) {
+                    double yr = 0.0, yi = 0.0;
+                    for (int32_t i = 0; i < ninput; ++i) {
+                        int64_t wx = ((int64_t)f * nbeam + b) * ninput + i;
+                        int64_t xx = (t * nchan + f) * (int64_t)ninput + i;
+                        yr += wre[wx] * xre[xx] - wim[wx] * xim[xx];
+                        yi += wre[wx] * xim[xx] + wim[wx] * xre[xx];
+                    }
+                    power += yr * yr + yi * yi;
+                }
+                out[((int64_t)b * nchan + f) * nout + u] = power;
+            }
+        }
+    }
+    return ORC_OK;
+}
