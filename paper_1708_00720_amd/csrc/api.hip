@@ -1,0 +1,386 @@
+// Host side of the C ABI: argument checking, plan bookkeeping, launches.
+//
+// Every check runs before anything is enqueued, so a rejected call leaves the
+// stream untouched.  No call here allocates device memory except
+// bfx_xengine_create_batched (its work list).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "bfx_internal.h"
+
+namespace bfx {
+
+static thread_local char g_detail[512];
+
+bfx_status fail(bfx_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_detail, sizeof g_detail, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+bfx_status hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorNotSupported) return fail(BFX_ENOTSUP, "%s: not built in this library", what);
+    return fail(BFX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Defined with the kernels.
+hipError_t launch_xengine_batched(bool ci4, const void *in, int64_t nt, const BatchUnit *units,
+                                  int32_t nunits, const int32_t *d_worklist, int64_t nwork,
+                                  int64_t t_offset_rows, int32_t *out, bool overwrite,
+                                  hipStream_t s);
+int xengine_tri_items(int32_t ninput);
+hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
+                              float *out, bool overwrite, hipStream_t s);
+hipError_t launch_dump(bool is_int, const void *acc, void *out, double *run64, int64_t n,
+                       hipStream_t s);
+hipError_t launch_fengine(const int8_t *in, int32_t ninput, int32_t nfft, int64_t nspec,
+                          const float *scale, void *out, bool ci8, hipStream_t s);
+hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t nchan,
+                           int32_t nbeam, int64_t ntime, int32_t navg, float *out, hipStream_t s);
+
+}  // namespace bfx
+
+using namespace bfx;
+
+struct Sub {
+    int32_t ninput;
+    int32_t nchan;
+};
+
+struct bfx_xengine {
+    bfx_dtype in;
+    bool batched;
+    std::vector<Sub> subs;
+    int64_t nacc;
+    // batched plans only
+    std::vector<BatchUnit> units_host;
+    int32_t *d_worklist;
+    int64_t nwork;
+};
+
+namespace {
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+inline int64_t in_sample_bytes(bfx_dtype d) {
+    switch (d) {
+        case BFX_CI4: return 1;
+        case BFX_CI8: return 2;
+        case BFX_CF16: return 4;
+        default: return 0;
+    }
+}
+
+inline int64_t out_pair_bytes(bfx_dtype d) { return 8; /* int32 pair or float pair */ }
+
+inline int64_t round256(int64_t x) { return (x + 255) / 256 * 256; }
+
+inline int64_t tri(int64_t n) { return n * (n + 1) / 2; }
+
+bfx_status check_dims(int32_t ninput, int32_t nchan) {
+    if (ninput <= 0 || ninput > 8192 || (ninput % 4) != 0)
+        return fail(BFX_EINVAL, "ninput=%d must be a positive multiple of 4 <= 8192", ninput);
+    if (nchan <= 0 || nchan > 65536)
+        return fail(BFX_EINVAL, "nchan=%d must be in [1, 65536]", nchan);
+    return BFX_OK;
+}
+
+// Offsets for subarray k of a plan, for a gulp of ntime samples.
+void offsets(const bfx_xengine *p, int32_t k, int64_t ntime, int64_t *in_off, int64_t *out_off) {
+    int64_t io = 0, oo = 0;
+    const int64_t sb = in_sample_bytes(p->in);
+    for (int32_t s = 0; s < k; ++s) {
+        io += round256(ntime * p->subs[s].nchan * p->subs[s].ninput * sb);
+        oo += round256(p->subs[s].nchan * tri(p->subs[s].ninput) * out_pair_bytes(p->in));
+    }
+    *in_off = io;
+    *out_off = oo;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bfx_strerror(bfx_status s) {
+    switch (s) {
+        case BFX_OK: return "BFX_OK: success";
+        case BFX_EINVAL: return "BFX_EINVAL: invalid argument";
+        case BFX_ERANGE: return "BFX_ERANGE: integration exceeds the int32 bound";
+        case BFX_EHIP: return "BFX_EHIP: HIP runtime error";
+        case BFX_ENOTSUP: return "BFX_ENOTSUP: not supported";
+        case BFX_ENOMEM: return "BFX_ENOMEM: allocation failed";
+    }
+    return "unknown bfx_status";
+}
+
+const char *bfx_last_error_detail(void) { return g_detail; }
+
+int64_t bfx_xengine_max_ntime(bfx_dtype in) {
+    switch (in) {
+        case BFX_CI8: return (int64_t)2147483647 / (2 * 128 * 128);  // 65535
+        case BFX_CI4: return (int64_t)2147483647 / (2 * 8 * 8);      // 16777215
+        case BFX_CF16: return INT64_MAX;
+        default: return -1;
+    }
+}
+
+bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan, bfx_dtype in) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan pointer is NULL");
+    *plan = nullptr;
+    if (in != BFX_CI4 && in != BFX_CI8 && in != BFX_CF16)
+        return fail(BFX_EINVAL, "input dtype %d is not ci4, ci8 or cf16", (int)in);
+    bfx_status st = check_dims(ninput, nchan);
+    if (st != BFX_OK) return st;
+    bfx_xengine *p = new (std::nothrow) bfx_xengine();
+    if (!p) return fail(BFX_ENOMEM, "host allocation of the plan failed");
+    p->in = in;
+    p->batched = false;
+    p->subs.push_back(Sub{ninput, nchan});
+    p->nacc = 0;
+    p->d_worklist = nullptr;
+    p->nwork = 0;
+    *plan = p;
+    return BFX_OK;
+}
+
+bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const int32_t *ninput,
+                                      const int32_t *nchan, bfx_dtype in) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan pointer is NULL");
+    *plan = nullptr;
+    if (nsub <= 0 || nsub > 4096 || !ninput || !nchan)
+        return fail(BFX_EINVAL, "nsub=%d must be in [1, 4096] with non-NULL size arrays", nsub);
+    if (in != BFX_CI4 && in != BFX_CI8)
+        return fail(BFX_ENOTSUP, "batched plans take ci4 or ci8 input");
+    int64_t nwork = 0;
+    for (int32_t k = 0; k < nsub; ++k) {
+        bfx_status st = check_dims(ninput[k], nchan[k]);
+        if (st != BFX_OK) return st;
+        nwork += (int64_t)nchan[k] * xengine_tri_items(ninput[k]);
+    }
+    if (nwork > (int64_t)1 << 30) return fail(BFX_EINVAL, "batched plan is too large");
+    bfx_xengine *p = new (std::nothrow) bfx_xengine();
+    if (!p) return fail(BFX_ENOMEM, "host allocation of the plan failed");
+    p->in = in;
+    p->batched = true;
+    p->nacc = 0;
+    p->d_worklist = nullptr;
+    for (int32_t k = 0; k < nsub; ++k) p->subs.push_back(Sub{ninput[k], nchan[k]});
+    // Work list: one entry per (subarray, channel, item), ordered by
+    // decreasing cost (larger arrays first) so the persistent grid drains
+    // evenly.  Entry = (unit << 20 | item) paired with the channel.
+    std::vector<int> order(nsub);
+    for (int k = 0; k < nsub; ++k) order[k] = k;
+    for (int a = 0; a < nsub; ++a)
+        for (int b = a + 1; b < nsub; ++b)
+            if (ninput[order[b]] > ninput[order[a]]) std::swap(order[a], order[b]);
+    std::vector<int32_t> work;
+    work.reserve((size_t)nwork * 2);
+    int32_t first = 0;
+    p->units_host.resize(nsub);
+    for (int k = 0; k < nsub; ++k) {
+        BatchUnit u{};
+        u.nchan = nchan[k];
+        u.ninput = ninput[k];
+        u.nitems = xengine_tri_items(ninput[k]);
+        u.first = first;
+        first += u.nchan * u.nitems;
+        p->units_host[k] = u;
+    }
+    for (int oi = 0; oi < nsub; ++oi) {
+        const int k = order[oi];
+        const BatchUnit &u = p->units_host[k];
+        for (int32_t it = 0; it < u.nitems; ++it)
+            for (int32_t f = 0; f < u.nchan; ++f) {
+                work.push_back((k << 20) | it);
+                work.push_back(f);
+            }
+    }
+    p->nwork = nwork;
+    hipError_t e = hipMalloc((void **)&p->d_worklist, work.size() * sizeof(int32_t));
+    if (e != hipSuccess) {
+        delete p;
+        return fail(BFX_ENOMEM, "hipMalloc of the work list failed: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->d_worklist, work.data(), work.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(p->d_worklist);
+        delete p;
+        return hip_fail(e, "copying the work list");
+    }
+    *plan = p;
+    return BFX_OK;
+}
+
+bfx_status bfx_xengine_destroy(bfx_xengine *plan) {
+    g_detail[0] = 0;
+    if (!plan) return BFX_OK;
+    if (plan->d_worklist) {
+        hipError_t e = hipFree(plan->d_worklist);
+        delete plan;
+        if (e != hipSuccess) return hip_fail(e, "freeing the work list");
+        return BFX_OK;
+    }
+    delete plan;
+    return BFX_OK;
+}
+
+size_t bfx_xengine_in_bytes(const bfx_xengine *plan, int64_t ntime) {
+    if (!plan || ntime < 0) return 0;
+    int64_t io, oo;
+    offsets(plan, (int32_t)plan->subs.size(), ntime, &io, &oo);
+    if (!plan->batched) {
+        const Sub &s = plan->subs[0];
+        return (size_t)(ntime * s.nchan * s.ninput * in_sample_bytes(plan->in));
+    }
+    return (size_t)io;
+}
+
+size_t bfx_xengine_out_bytes(const bfx_xengine *plan) {
+    if (!plan) return 0;
+    if (!plan->batched) {
+        const Sub &s = plan->subs[0];
+        return (size_t)(s.nchan * tri(s.ninput) * out_pair_bytes(plan->in));
+    }
+    int64_t io, oo;
+    offsets(plan, (int32_t)plan->subs.size(), 0, &io, &oo);
+    return (size_t)oo;
+}
+
+bfx_status bfx_xengine_sub_offsets(const bfx_xengine *plan, int32_t k, int64_t ntime,
+                                   int64_t *in_offset, int64_t *out_offset) {
+    g_detail[0] = 0;
+    if (!plan || !in_offset || !out_offset) return fail(BFX_EINVAL, "NULL argument");
+    if (k < 0 || k >= (int32_t)plan->subs.size())
+        return fail(BFX_EINVAL, "subarray %d out of range [0, %d)", k, (int)plan->subs.size());
+    if (ntime < 0) return fail(BFX_EINVAL, "ntime=%lld is negative", (long long)ntime);
+    offsets(plan, k, ntime, in_offset, out_offset);
+    return BFX_OK;
+}
+
+int64_t bfx_xengine_nacc(const bfx_xengine *plan) { return plan ? plan->nacc : -1; }
+
+bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t ntime, void *d_acc,
+                                  uint32_t flags, bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan is NULL");
+    if (!d_in || !d_acc) return fail(BFX_EINVAL, "d_in / d_acc must be device pointers, got NULL");
+    if (!aligned16(d_in) || !aligned16(d_acc))
+        return fail(BFX_EINVAL, "d_in / d_acc must be 16-byte aligned");
+    if (ntime <= 0) return fail(BFX_EINVAL, "ntime=%lld must be positive", (long long)ntime);
+    if (flags & ~BFX_ACC_OVERWRITE) return fail(BFX_EINVAL, "unknown flag bits 0x%x", flags);
+    const bool overwrite = flags & BFX_ACC_OVERWRITE;
+    const int64_t base = overwrite ? 0 : plan->nacc;
+    const int64_t tmax = bfx_xengine_max_ntime(plan->in);
+    if (ntime > tmax - base)
+        return fail(BFX_ERANGE,
+                    "%lld samples already accumulated + %lld new exceed the int32-exact bound "
+                    "%lld for this dtype; dump and start a new integration",
+                    (long long)base, (long long)ntime, (long long)tmax);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (plan->in == BFX_CF16) {
+        const Sub &sb = plan->subs[0];
+        e = launch_xengine_f16(d_in, ntime, sb.nchan, sb.ninput, (float *)d_acc, overwrite, s);
+    } else {
+        const bool ci4 = plan->in == BFX_CI4;
+        const int64_t row_bytes_per_input = ci4 ? 1 : 2;
+        // Integer launches are split so no launch sums more than
+        // kLaunchMaxTime samples in its int32 registers.
+        for (int64_t t0 = 0; t0 < ntime && e == hipSuccess; t0 += kLaunchMaxTime) {
+            const int64_t nt = ntime - t0 < kLaunchMaxTime ? ntime - t0 : kLaunchMaxTime;
+            const bool ow = overwrite && t0 == 0;
+            if (!plan->batched) {
+                const Sub &sb = plan->subs[0];
+                const uint8_t *src =
+                    (const uint8_t *)d_in + t0 * sb.nchan * sb.ninput * row_bytes_per_input;
+                e = launch_xengine_int(ci4, src, nt, sb.nchan, sb.ninput, (int32_t *)d_acc, ow, s);
+            } else {
+                std::vector<BatchUnit> u = plan->units_host;
+                for (size_t k = 0; k < u.size(); ++k) {
+                    int64_t io, oo;
+                    offsets(plan, (int32_t)k, ntime, &io, &oo);
+                    u[k].in_off = io;
+                    u[k].out_off = oo / 4;
+                }
+                e = launch_xengine_batched(ci4, d_in, nt, u.data(), (int32_t)u.size(),
+                                           plan->d_worklist, plan->nwork, t0, (int32_t *)d_acc, ow,
+                                           s);
+            }
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "X-engine launch");
+    plan->nacc = base + ntime;
+    return BFX_OK;
+}
+
+bfx_status bfx_xengine_dump(bfx_xengine *plan, const void *d_acc, void *d_out, double *d_run64,
+                            bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan is NULL");
+    if (!d_acc) return fail(BFX_EINVAL, "d_acc is NULL");
+    if (!aligned16(d_acc) || (d_out && !aligned16(d_out)) || (d_run64 && !aligned16(d_run64)))
+        return fail(BFX_EINVAL, "buffers must be 16-byte aligned");
+    const int64_t nbytes = (int64_t)bfx_xengine_out_bytes(plan);
+    const int64_t n = nbytes / 4;  // scalar elements (int32 or float)
+    const bool is_int = plan->in != BFX_CF16;
+    hipStream_t s = (hipStream_t)stream;
+    const bool copy = d_out && d_out != d_acc;
+    if (!copy && !d_run64) return BFX_OK;
+    if (plan->batched && d_run64)
+        return fail(BFX_ENOTSUP, "running sums of batched arenas are not supported");
+    hipError_t e = launch_dump(is_int, d_acc, copy ? d_out : nullptr, d_run64, n, s);
+    if (e != hipSuccess) return hip_fail(e, "dump launch");
+    return BFX_OK;
+}
+
+bfx_status bfx_fengine(const int8_t *d_in, int32_t ninput, int32_t nfft, int64_t nspec,
+                       const float *d_scale, void *d_out, bfx_dtype out, bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!d_in || !d_out) return fail(BFX_EINVAL, "d_in / d_out is NULL");
+    if (!aligned16(d_in) || !aligned16(d_out))
+        return fail(BFX_EINVAL, "d_in / d_out must be 16-byte aligned");
+    if (out != BFX_CI8 && out != BFX_CF32)
+        return fail(BFX_EINVAL, "output dtype must be BFX_CI8 or BFX_CF32");
+    if (out == BFX_CI8 && !d_scale) return fail(BFX_EINVAL, "ci8 output needs d_scale");
+    if (nfft < 64 || nfft > 8192 || (nfft & (nfft - 1)))
+        return fail(BFX_EINVAL, "nfft=%d must be a power of two in [64, 8192]", nfft);
+    if (ninput <= 0 || (ninput & 1) || ninput > 65536)
+        return fail(BFX_EINVAL, "ninput=%d must be positive and even", ninput);
+    if (nspec <= 0 || nspec > ((int64_t)1 << 31))
+        return fail(BFX_EINVAL, "nspec=%lld out of range", (long long)nspec);
+    hipError_t e = launch_fengine(d_in, ninput, nfft, nspec, d_scale, d_out, out == BFX_CI8,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "F-engine launch");
+    return BFX_OK;
+}
+
+bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput, int32_t nchan,
+                               int32_t nbeam, int64_t ntime, int32_t navg, float *d_out,
+                               bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!d_x || !d_w || !d_out) return fail(BFX_EINVAL, "NULL buffer");
+    if (!aligned16(d_x) || !aligned16(d_w) || !aligned16(d_out))
+        return fail(BFX_EINVAL, "buffers must be 16-byte aligned");
+    if (ninput <= 0 || ninput % 32 || ninput > 8192)
+        return fail(BFX_EINVAL, "ninput=%d must be a positive multiple of 32", ninput);
+    if (nchan <= 0 || nchan > 65536) return fail(BFX_EINVAL, "nchan=%d out of range", nchan);
+    if (nbeam <= 0 || nbeam > 256) return fail(BFX_EINVAL, "nbeam=%d must be in [1, 256]", nbeam);
+    if (navg <= 0 || ntime <= 0 || ntime % navg)
+        return fail(BFX_EINVAL, "ntime=%lld must be a positive multiple of navg=%d",
+                    (long long)ntime, navg);
+    hipError_t e = launch_beamform(d_x, d_w, ninput, nchan, nbeam, ntime, navg, d_out,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "beamformer launch");
+    return BFX_OK;
+}
+
+}  // extern "C"
