@@ -77,6 +77,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-timing-reps", type=int, default=50)
+    ap.add_argument("--profile-launches", type=int, default=0,
+                    help="only run this many X-engine launches on one gulp (for counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the X-engine "
@@ -93,6 +97,28 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        # known traffic: reads 1 GiB, writes 1 GiB
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30}), flush=True)
+        return
+    if args.profile_launches:
+        raw = synth.voltages(2, N_TIME, N_CHAN, N_INPUT, "ci4", 2.5, 7, gulp=0)
+        d_in = torch.from_numpy(raw.reshape(-1)).to(dev)
+        plan = bfx.bfx_xengine_create(N_INPUT, N_CHAN, "ci4")
+        vis = bfx.visibilities_buffer(plan, device=dev)
+        for _ in range(args.profile_launches):
+            bfx.bfx_xengine_accumulate(plan, d_in, N_TIME, vis, overwrite=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_launches": args.profile_launches}), flush=True)
+        plan.close()
+        return
 
     # ---- inputs: 4 distinct gulps, one per ring slot, resident in HBM
     gulp_bytes = N_TIME * N_CHAN * N_INPUT
