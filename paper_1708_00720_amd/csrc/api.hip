@@ -42,6 +42,7 @@ hipError_t launch_dump(bool is_int, const void *acc, void *out, double *run64, i
                        hipStream_t s);
 hipError_t launch_fengine(const int8_t *in, int32_t ninput, int32_t nfft, int64_t nspec,
                           const float *scale, void *out, bool ci8, hipStream_t s);
+bool fengine_supported(int32_t ninput, int32_t nfft);
 hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t nchan,
                            int32_t nbeam, int64_t ntime, int32_t navg, float *out, hipStream_t s);
 
@@ -355,8 +356,11 @@ bfx_status bfx_fengine(const int8_t *d_in, int32_t ninput, int32_t nfft, int64_t
         return fail(BFX_EINVAL, "nfft=%d must be a power of two in [64, 8192]", nfft);
     if (ninput <= 0 || (ninput & 1) || ninput > 65536)
         return fail(BFX_EINVAL, "ninput=%d must be positive and even", ninput);
-    if (nspec <= 0 || nspec > ((int64_t)1 << 31))
+    if (nspec <= 0 || nspec > ((int64_t)1 << 28))
         return fail(BFX_EINVAL, "nspec=%lld out of range", (long long)nspec);
+    if (!fengine_supported(ninput, nfft))
+        return fail(BFX_ENOTSUP, "this build transforms nfft=4096 with ninput a multiple of 16 "
+                                 "(got nfft=%d, ninput=%d)", nfft, ninput);
     hipError_t e = launch_fengine(d_in, ninput, nfft, nspec, d_scale, d_out, out == BFX_CI8,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "F-engine launch");

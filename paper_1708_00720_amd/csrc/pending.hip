@@ -14,10 +14,6 @@ hipError_t launch_xengine_f16(const void *, int64_t, int32_t, int32_t, float *, 
                               hipStream_t) {
     return hipErrorNotSupported;
 }
-hipError_t launch_fengine(const int8_t *, int32_t, int32_t, int64_t, const float *, void *, bool,
-                          hipStream_t) {
-    return hipErrorNotSupported;
-}
 hipError_t launch_beamform(const void *, const void *, int32_t, int32_t, int32_t, int64_t,
                            int32_t, float *, hipStream_t) {
     return hipErrorNotSupported;
