@@ -102,11 +102,19 @@ int64_t bfx_xengine_max_ntime(bfx_dtype in);
  * memory is allocated.  On success *plan receives the new plan.            */
 bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan, bfx_dtype in);
 
-/* Create a batched plan: `nsub` independent arrays (subarrays / subbands) of
- * ninput[k] inputs and nchan[k] channels, correlated by one launch.  Inputs
- * and outputs live in two arenas; bfx_xengine_sub_offsets gives where each
- * subarray's gulp and visibilities start.  Allocates a device work list on
- * the current device (BFX_ENOMEM / BFX_EHIP on failure).                    */
+/* Create a batched plan: `nsub` (<= 4096) independent arrays (subarrays /
+ * subbands) of ninput[k] inputs and nchan[k] channels, correlated by one
+ * persistent launch (ci4 or ci8 input; at most 2^24 work items in all).
+ * Inputs and outputs live in two arenas, subarrays in order k = 0, 1, ...:
+ *   input arena:  subarray k's gulp is [ntime][nchan_k][ninput_k] contiguous
+ *                 and occupies ntime * R_k bytes, R_k = its row bytes rounded
+ *                 up to a multiple of 256 (so offsets scale with ntime);
+ *   output arena: subarray k's [nchan_k][p][2] visibilities, each block
+ *                 rounded up to a multiple of 256 bytes.
+ * bfx_xengine_sub_offsets gives both offsets.  Allocates the device work
+ * list and subarray table on the current device (BFX_ENOMEM / BFX_EHIP on
+ * failure); accumulate on a batched plan must run on that device.  Results
+ * are bit-identical to one plain plan per subarray.                         */
 bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const int32_t *ninput,
                                       const int32_t *nchan, bfx_dtype in);
 
@@ -184,8 +192,10 @@ bfx_status bfx_fengine(const int8_t *d_in, int32_t ninput, int32_t nfft, int64_t
  *          without conjugation: y[b][f][t] = sum_i w[f][b][i] * x[t][f][i];
  *   d_out  device float [nbeam][nchan][ntime/navg]:
  *          P[b][f][u] = sum_{t=u*navg}^{u*navg+navg-1} |y[b][f][t]|^2.
- * ntime must be a positive multiple of navg; ninput a positive multiple of
- * 32; nbeam in [1, 256].  FP16 products, FP32 accumulation.                 */
+ * ntime must be a positive multiple of navg (<= 2^30); ninput a positive
+ * multiple of 32 (<= 8192); nbeam in [1, 256].  binary16 products, binary32
+ * accumulation of y and of P.  This build integrates navg = 1, 2, 4, 8, 16 or
+ * 32 samples and returns BFX_ENOTSUP for other valid navg.                   */
 bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput, int32_t nchan,
                                int32_t nbeam, int64_t ntime, int32_t navg, float *d_out,
                                bfx_stream stream);

@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -31,10 +32,6 @@ bfx_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Defined with the kernels.
-hipError_t launch_xengine_batched(bool ci4, const void *in, int64_t nt, const BatchUnit *units,
-                                  int32_t nunits, const int32_t *d_worklist, int64_t nwork,
-                                  int64_t t_offset_rows, int32_t *out, bool overwrite,
-                                  hipStream_t s);
 int xengine_tri_items(int32_t ninput);
 hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               float *out, bool overwrite, hipStream_t s);
@@ -45,6 +42,7 @@ hipError_t launch_fengine(const int8_t *in, int32_t ninput, int32_t nfft, int64_
 bool fengine_supported(int32_t ninput, int32_t nfft);
 hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t nchan,
                            int32_t nbeam, int64_t ntime, int32_t navg, float *out, hipStream_t s);
+bool beamform_supported(int32_t navg);
 
 }  // namespace bfx
 
@@ -60,9 +58,9 @@ struct bfx_xengine {
     bool batched;
     std::vector<Sub> subs;
     int64_t nacc;
-    // batched plans only
-    std::vector<BatchUnit> units_host;
-    int32_t *d_worklist;
+    // batched plans only: device unit table and work list
+    BatchUnit *d_units;
+    int2 *d_work;
     int64_t nwork;
 };
 
@@ -93,16 +91,47 @@ bfx_status check_dims(int32_t ninput, int32_t nchan) {
     return BFX_OK;
 }
 
-// Offsets for subarray k of a plan, for a gulp of ntime samples.
+// Offsets for subarray k of a plan, for a gulp of ntime samples.  Each
+// subarray's time row is padded to 256 bytes in the arena layout, so its
+// input offset is ntime times a per-plan constant.
 void offsets(const bfx_xengine *p, int32_t k, int64_t ntime, int64_t *in_off, int64_t *out_off) {
     int64_t io = 0, oo = 0;
     const int64_t sb = in_sample_bytes(p->in);
     for (int32_t s = 0; s < k; ++s) {
-        io += round256(ntime * p->subs[s].nchan * p->subs[s].ninput * sb);
+        io += round256((int64_t)p->subs[s].nchan * p->subs[s].ninput * sb);
         oo += round256(p->subs[s].nchan * tri(p->subs[s].ninput) * out_pair_bytes(p->in));
     }
-    *in_off = io;
+    *in_off = io * ntime;
     *out_off = oo;
+}
+
+// Work list of a batched plan.  Every work item costs the same (a fixed
+// number of LDS stages, whatever its tile count), so balance is by item
+// count: channels, largest first, go whole to the least loaded of 8 queues
+// (one per XCD, so a channel's items share an L2 and run side by side); the
+// queues are padded to equal length and interleaved (entry 8q + x = item q of
+// queue x).
+std::vector<int2> build_work(const std::vector<BatchUnit> &units) {
+    struct Chan { int32_t k, f, n; };
+    std::vector<Chan> chans;
+    for (int32_t k = 0; k < (int32_t)units.size(); ++k)
+        for (int32_t f = 0; f < units[k].nchan; ++f) chans.push_back(Chan{k, f, units[k].nitems});
+    std::stable_sort(chans.begin(), chans.end(),
+                     [](const Chan &a, const Chan &b) { return a.n > b.n; });
+    std::vector<int2> q[8];
+    for (const Chan &c : chans) {
+        int best = 0;
+        for (int x = 1; x < 8; ++x)
+            if (q[x].size() < q[best].size()) best = x;
+        for (int32_t it = 0; it < c.n; ++it)
+            q[best].push_back(int2{c.k | (it << kBatchSubBits), c.f});
+    }
+    size_t len = 0;
+    for (int x = 0; x < 8; ++x) len = q[x].size() > len ? q[x].size() : len;
+    std::vector<int2> work(8 * len, int2{-1, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t i = 0; i < q[x].size(); ++i) work[8 * i + x] = q[x][i];
+    return work;
 }
 
 }  // namespace
@@ -146,7 +175,8 @@ bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan,
     p->batched = false;
     p->subs.push_back(Sub{ninput, nchan});
     p->nacc = 0;
-    p->d_worklist = nullptr;
+    p->d_units = nullptr;
+    p->d_work = nullptr;
     p->nwork = 0;
     *plan = p;
     return BFX_OK;
@@ -167,53 +197,46 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
         if (st != BFX_OK) return st;
         nwork += (int64_t)nchan[k] * xengine_tri_items(ninput[k]);
     }
-    if (nwork > (int64_t)1 << 30) return fail(BFX_EINVAL, "batched plan is too large");
+    if (nwork > (int64_t)1 << 24)
+        return fail(BFX_EINVAL, "batched plan has %lld work items (limit 2^24)", (long long)nwork);
     bfx_xengine *p = new (std::nothrow) bfx_xengine();
     if (!p) return fail(BFX_ENOMEM, "host allocation of the plan failed");
     p->in = in;
     p->batched = true;
     p->nacc = 0;
-    p->d_worklist = nullptr;
+    p->d_units = nullptr;
+    p->d_work = nullptr;
     for (int32_t k = 0; k < nsub; ++k) p->subs.push_back(Sub{ninput[k], nchan[k]});
-    // Work list: one entry per (subarray, channel, item), ordered by
-    // decreasing cost (larger arrays first) so the persistent grid drains
-    // evenly.  Entry = (unit << 20 | item) paired with the channel.
-    std::vector<int> order(nsub);
-    for (int k = 0; k < nsub; ++k) order[k] = k;
-    for (int a = 0; a < nsub; ++a)
-        for (int b = a + 1; b < nsub; ++b)
-            if (ninput[order[b]] > ninput[order[a]]) std::swap(order[a], order[b]);
-    std::vector<int32_t> work;
-    work.reserve((size_t)nwork * 2);
-    int32_t first = 0;
-    p->units_host.resize(nsub);
-    for (int k = 0; k < nsub; ++k) {
-        BatchUnit u{};
+    std::vector<BatchUnit> units(nsub);
+    for (int32_t k = 0; k < nsub; ++k) {
+        int64_t row_off, out_off;
+        offsets(p, k, 1, &row_off, &out_off);
+        BatchUnit &u = units[k];
+        u.in_row_off = row_off;
+        u.t_stride = (int64_t)nchan[k] * ninput[k] * in_sample_bytes(in);
+        u.out_off = out_off;
         u.nchan = nchan[k];
         u.ninput = ninput[k];
+        u.nb = (ninput[k] + 63) / 64;
         u.nitems = xengine_tri_items(ninput[k]);
-        u.first = first;
-        first += u.nchan * u.nitems;
-        p->units_host[k] = u;
     }
-    for (int oi = 0; oi < nsub; ++oi) {
-        const int k = order[oi];
-        const BatchUnit &u = p->units_host[k];
-        for (int32_t it = 0; it < u.nitems; ++it)
-            for (int32_t f = 0; f < u.nchan; ++f) {
-                work.push_back((k << 20) | it);
-                work.push_back(f);
-            }
-    }
-    p->nwork = nwork;
-    hipError_t e = hipMalloc((void **)&p->d_worklist, work.size() * sizeof(int32_t));
+    const std::vector<int2> work = build_work(units);
+    p->nwork = (int64_t)work.size();
+    hipError_t e = hipMalloc((void **)&p->d_units, units.size() * sizeof(BatchUnit));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_work, work.size() * sizeof(int2));
     if (e != hipSuccess) {
+        hipFree(p->d_units);
         delete p;
-        return fail(BFX_ENOMEM, "hipMalloc of the work list failed: %s", hipGetErrorString(e));
+        return fail(BFX_ENOMEM, "device allocation of the work list failed: %s",
+                    hipGetErrorString(e));
     }
-    e = hipMemcpy(p->d_worklist, work.data(), work.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(p->d_units, units.data(), units.size() * sizeof(BatchUnit),
+                  hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        hipFree(p->d_worklist);
+        hipFree(p->d_units);
+        hipFree(p->d_work);
         delete p;
         return hip_fail(e, "copying the work list");
     }
@@ -224,13 +247,14 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
 bfx_status bfx_xengine_destroy(bfx_xengine *plan) {
     g_detail[0] = 0;
     if (!plan) return BFX_OK;
-    if (plan->d_worklist) {
-        hipError_t e = hipFree(plan->d_worklist);
-        delete plan;
-        if (e != hipSuccess) return hip_fail(e, "freeing the work list");
-        return BFX_OK;
+    hipError_t e = hipSuccess;
+    if (plan->d_units) e = hipFree(plan->d_units);
+    if (plan->d_work) {
+        hipError_t e2 = hipFree(plan->d_work);
+        if (e == hipSuccess) e = e2;
     }
     delete plan;
+    if (e != hipSuccess) return hip_fail(e, "freeing the work list");
     return BFX_OK;
 }
 
@@ -289,8 +313,15 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (plan->in == BFX_CF16) {
+        // binary32 accumulation has no integer bound; launches are still cut
+        // at kLaunchMaxTime rows so the kernel's row counter stays 32-bit.
         const Sub &sb = plan->subs[0];
-        e = launch_xengine_f16(d_in, ntime, sb.nchan, sb.ninput, (float *)d_acc, overwrite, s);
+        for (int64_t t0 = 0; t0 < ntime && e == hipSuccess; t0 += kLaunchMaxTime) {
+            const int64_t nt = ntime - t0 < kLaunchMaxTime ? ntime - t0 : kLaunchMaxTime;
+            const uint8_t *src = (const uint8_t *)d_in + t0 * sb.nchan * sb.ninput * 4;
+            e = launch_xengine_f16(src, nt, sb.nchan, sb.ninput, (float *)d_acc,
+                                   overwrite && t0 == 0, s);
+        }
     } else {
         const bool ci4 = plan->in == BFX_CI4;
         const int64_t row_bytes_per_input = ci4 ? 1 : 2;
@@ -305,16 +336,8 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
                     (const uint8_t *)d_in + t0 * sb.nchan * sb.ninput * row_bytes_per_input;
                 e = launch_xengine_int(ci4, src, nt, sb.nchan, sb.ninput, (int32_t *)d_acc, ow, s);
             } else {
-                std::vector<BatchUnit> u = plan->units_host;
-                for (size_t k = 0; k < u.size(); ++k) {
-                    int64_t io, oo;
-                    offsets(plan, (int32_t)k, ntime, &io, &oo);
-                    u[k].in_off = io;
-                    u[k].out_off = oo / 4;
-                }
-                e = launch_xengine_batched(ci4, d_in, nt, u.data(), (int32_t)u.size(),
-                                           plan->d_worklist, plan->nwork, t0, (int32_t *)d_acc, ow,
-                                           s);
+                e = launch_xengine_batched(ci4, d_in, ntime, t0, nt, plan->d_units, plan->d_work,
+                                           plan->nwork, d_acc, ow, s);
             }
         }
     }
@@ -378,9 +401,12 @@ bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput,
         return fail(BFX_EINVAL, "ninput=%d must be a positive multiple of 32", ninput);
     if (nchan <= 0 || nchan > 65536) return fail(BFX_EINVAL, "nchan=%d out of range", nchan);
     if (nbeam <= 0 || nbeam > 256) return fail(BFX_EINVAL, "nbeam=%d must be in [1, 256]", nbeam);
-    if (navg <= 0 || ntime <= 0 || ntime % navg)
-        return fail(BFX_EINVAL, "ntime=%lld must be a positive multiple of navg=%d",
+    if (navg <= 0 || ntime <= 0 || ntime % navg || ntime > ((int64_t)1 << 30))
+        return fail(BFX_EINVAL, "ntime=%lld must be a positive multiple of navg=%d, <= 2^30",
                     (long long)ntime, navg);
+    if (!beamform_supported(navg))
+        return fail(BFX_ENOTSUP, "this build integrates navg = 1, 2, 4, 8, 16 or 32 samples "
+                                 "(got %d)", navg);
     hipError_t e = launch_beamform(d_x, d_w, ninput, nchan, nbeam, ntime, navg, d_out,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "beamformer launch");

@@ -22,14 +22,30 @@ constexpr int64_t kLaunchMaxTime = 65535;
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan,
                               int32_t ninput, int32_t *out, bool overwrite, hipStream_t s);
 
-// One work unit of a batched (multi-array) integer launch.
+// Per-subarray record of a batched plan (device table, built at plan
+// creation).  Subarray k's gulp of ntime samples starts at byte
+// ntime * in_row_off of the input arena and is [ntime][nchan][ninput]
+// contiguous (t_stride bytes per time row); its visibilities start at byte
+// out_off of the output arena.
 struct BatchUnit {
-    int64_t in_off;   // byte offset of the subarray's gulp in the input arena
-    int64_t out_off;  // int32 offset of its visibilities in the output arena
+    int64_t in_row_off;  // sum over earlier subarrays of their 256-byte-padded row bytes
+    int64_t t_stride;    // nchan * ninput * bytes per sample
+    int64_t out_off;     // byte offset in the output arena
     int32_t nchan;
     int32_t ninput;
-    int32_t nitems;   // work items per channel (triangle tiles)
-    int32_t first;    // index of this subarray's first work item in the flat list
+    int32_t nitems;      // work items per channel (triangle tiles)
+    int32_t nb;          // input blocks of 64
 };
+
+// Work-list entry of a batched launch: x = subarray | item << 12 (x < 0: a
+// padding entry), y = channel.
+constexpr int kBatchSubBits = 12;
+
+// Integer X-engine over a batched plan: `nwork` work-list entries (a multiple
+// of 8; entry B runs on XCD B % 8), time rows [t0, t0 + nt) of every
+// subarray's gulp of ntime samples.
+hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, int64_t t0,
+                                  int64_t nt, const BatchUnit *d_units, const int2 *d_work,
+                                  int64_t nwork, void *out, bool overwrite, hipStream_t s);
 
 }  // namespace bfx

@@ -1,0 +1,427 @@
+// Shared machinery of the X-engine kernels (integer and binary16): work
+// decomposition of the lower triangle, the LDS stage ring fed by direct
+// global->LDS DMA, and the persistent producer/consumer loop.  The element
+// arithmetic (fragment reads, MFMA, epilogue) is supplied by a consumer
+// policy per input format.
+//
+// Work decomposition.  Inputs are grouped in blocks of 64.  One workgroup
+// (8 waves, two per SIMD) holds up to four input blocks of one channel in LDS
+// and produces up to four 64x64 block pairs (I >= J) of the triangle, each
+// split between two waves (64 rows x 32 columns each).  The block pairs of a
+// channel are packed into work items in closed form (decode_item): 2x2
+// super-tiles below the diagonal, diagonal super-tiles that borrow a pair from
+// the odd last block row, and the rest of that row in groups of three.  The
+// grid is persistent (one workgroup per CU); workgroup b walks the flat work
+// ids b, b + grid, ...; a work source maps a flat id to (channel, item).
+//
+// Data path.  A ring of kRing LDS stages of 16 KiB receives raw time rows of
+// the four blocks (256 inputs) straight from HBM with global_load_lds_dwordx4
+// (no staging registers), kRing-1 stages ahead of the MFMA work and across
+// work-item boundaries; every wave issues two of each stage's 16 DMA
+// instructions and waits on its own vector-memory counter before the stage
+// barrier.  Each row's 16-byte chunks are XOR-swizzled by the row index so the
+// consumers' transposing LDS reads are free of bank conflicts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfx {
+namespace {
+
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) v2i lds_v2i;
+typedef __attribute__((address_space(3))) v4s lds_v4s;
+
+constexpr int kBlk = 64;          // inputs per block / LDS slot
+constexpr int kSlots = 4;         // input blocks held per work item
+constexpr int kWaves = 8;         // two block-pair halves per SIMD
+constexpr int kDmaWaves = kWaves; // every wave issues part of each stage's DMA
+constexpr int kThreads = 64 * kWaves;
+constexpr int kStageBytes = 16384;
+constexpr int kRing = 8;          // LDS stages in flight (128 KiB)
+constexpr int kLdsBytes = kRing * kStageBytes;
+constexpr int kDmaPerWave = kStageBytes / 1024 / kDmaWaves;  // 16-byte-per-lane DMA instructions
+
+// Layout of one LDS stage: kT time rows of 256 inputs of BPS bytes each
+// (1: ci4, 2: ci8, 4: cf16).
+template <int BPS>
+struct RowFmt {
+    static constexpr int kBps = BPS;                    // bytes per sample
+    static constexpr int kRow = kSlots * kBlk * kBps;   // bytes per time row
+    static constexpr int kT = kStageBytes / kRow;       // time rows per stage (64 / 32 / 16)
+    static constexpr int kChunks = kRow / 16;           // 16-byte chunks per row
+    static constexpr int kChunksPerSlot = kChunks / kSlots;
+    static constexpr int kInputsPerChunk = 16 / kBps;
+    static constexpr int kRowsPerDma = 1024 / kRow;     // rows covered by one wave DMA
+    static_assert(kRowsPerDma >= 1, "a wave DMA must cover whole rows");
+    // XOR swizzle of the 16-byte chunks of row t.  A transposing read touches
+    // rows t0..t0+7 (ds_read_b64_tr_b8) or t0..t0+3 (ds_read_b64_tr_b16) of
+    // adjacent chunks per 16-lane group; these swizzles map the chunks read
+    // by a 32-lane half to distinct bank groups.
+    __device__ static inline int swz(int t) { return BPS == 1 ? ((t & 7) << 1) : ((t & 3) << 2); }
+};
+
+struct Task {
+    int blk[kSlots];  // input block held by each LDS slot, -1 = unused
+    int rs[4];        // per block pair: LDS slot of its row block, -1 = unused
+    int cs[4];        // per block pair: LDS slot of its column block
+};
+
+__host__ __device__ inline int tri_items(int nb) {
+    int h = nb / 2;
+    int s = h * (h + 1) / 2;
+    if (nb & 1) s += (h == 0) ? 1 : (h + 2) / 3;
+    return s;
+}
+
+// Closed-form packing of the lower-triangle block pairs of an nb x nb grid.
+__device__ inline void decode_item(int nb, int item, Task &tk) {
+    const int h = nb / 2;
+    const int S = h * (h + 1) / 2;
+    const bool odd = nb & 1;
+    for (int k = 0; k < 4; ++k) { tk.blk[k] = -1; tk.rs[k] = -1; tk.cs[k] = -1; }
+    if (item < S) {
+        int a = (int)((sqrtf(8.0f * item + 1.0f) - 1.0f) * 0.5f);
+        while ((a + 1) * (a + 2) / 2 <= item) ++a;
+        while (a * (a + 1) / 2 > item) --a;
+        const int b = item - a * (a + 1) / 2;
+        if (b < a) {
+            tk.blk[0] = 2 * a; tk.blk[1] = 2 * a + 1; tk.blk[2] = 2 * b; tk.blk[3] = 2 * b + 1;
+            tk.rs[0] = 0; tk.cs[0] = 2;
+            tk.rs[1] = 0; tk.cs[1] = 3;
+            tk.rs[2] = 1; tk.cs[2] = 2;
+            tk.rs[3] = 1; tk.cs[3] = 3;
+        } else {
+            tk.blk[0] = 2 * a; tk.blk[1] = 2 * a + 1;
+            tk.rs[0] = 0; tk.cs[0] = 0;
+            tk.rs[1] = 1; tk.cs[1] = 0;
+            tk.rs[2] = 1; tk.cs[2] = 1;
+            if (odd) { tk.blk[2] = nb - 1; tk.rs[3] = 2; tk.cs[3] = 0; }
+        }
+    } else {
+        const int g = item - S;
+        tk.blk[0] = nb - 1;
+        for (int w = 0; w < 3; ++w) {
+            const int k = 3 * g + w;
+            if (k < h) { tk.blk[w + 1] = 2 * k + 1; tk.rs[w] = 0; tk.cs[w] = w + 1; }
+        }
+        if (g == 0) { tk.rs[3] = 0; tk.cs[3] = 0; }
+    }
+}
+
+// Select element k of a 4-element task array without dynamic indexing (which
+// would place the array in scratch or LDS).
+__device__ inline int pick4(const int (&a)[4], int k) {
+    return k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+}
+
+__device__ inline uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// 16 bytes from global memory straight into LDS at m0 + 16 * lane.  Issued as
+// inline assembly so that the compiler does not serialise the ring with its
+// own conservative waits; completion is tracked by the explicit vmcnt waits.
+__device__ inline void dma16(const void *src, uint32_t lds_wave_base) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_wave_base)), "v"(src)
+                 : "memory", "m0");
+}
+
+// Wait until at most N vector-memory operations of this wave are in flight
+// (gfx9 encoding: vmcnt split over bits 3:0 and 15:14; expcnt and lgkmcnt
+// left at their maxima).
+template <int N>
+__device__ inline void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Wait until every DMA issued for stages up to the awaited one has landed,
+// given `ahead` stages issued after it (each kDmaPerWave instructions).
+__device__ __forceinline__ void wait_stage(int ahead) {
+    static_assert(kRing - 2 <= 6, "extend the cases below");
+    switch (ahead) {
+        case 6: wait_vm<6 * kDmaPerWave>(); break;
+        case 5: wait_vm<5 * kDmaPerWave>(); break;
+        case 4: wait_vm<4 * kDmaPerWave>(); break;
+        case 3: wait_vm<3 * kDmaPerWave>(); break;
+        case 2: wait_vm<2 * kDmaPerWave>(); break;
+        case 1: wait_vm<1 * kDmaPerWave>(); break;
+        default: wait_vm<0>(); break;
+    }
+}
+
+__device__ inline void block_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+__device__ const uint4 kZeroChunk = {0u, 0u, 0u, 0u};
+
+// Scheduling masks of __builtin_amdgcn_sched_group_barrier.
+constexpr int kSchedValu = 0x2;
+constexpr int kSchedMfma = 0x8;
+
+// Per-wave view of the current compute item: wave w works on block pair
+// w % 4 of the item, column half w / 4 (the two waves of a pair share a SIMD).
+struct WaveJob {
+    int rblk, cblk, ch;
+    int rrow, crow;  // LDS input offsets of the row block and of this wave's column half
+    bool active, diag, full;
+    unsigned live;   // bit r: sub-block (row half r, this column half) is needed
+};
+
+__device__ inline WaveJob make_job(const Task &tk, int wave, int ninput) {
+    WaveJob j;
+    const int pw = wave & 3;
+    j.ch = wave >> 2;
+    const int rs = pick4(tk.rs, pw);
+    const int cs = pick4(tk.cs, pw);
+    j.active = rs >= 0;
+    j.rblk = j.active ? pick4(tk.blk, rs) : 0;
+    j.cblk = j.active ? pick4(tk.blk, cs) : 0;
+    j.rrow = (rs < 0 ? 0 : rs) * kBlk;
+    j.crow = (cs < 0 ? 0 : cs) * kBlk + 32 * j.ch;
+    j.diag = j.active && rs == cs;
+    j.live = 0;
+    if (j.active) {
+        for (int r = 0; r < 2; ++r) {
+            const bool ok = j.rblk * kBlk + 32 * r < ninput && j.cblk * kBlk + 32 * j.ch < ninput &&
+                            !(j.diag && r == 0 && j.ch == 1);
+            if (ok) j.live |= 1u << r;
+        }
+    }
+    j.active = j.live != 0;
+    j.full = j.live == 3u;
+    return j;
+}
+
+// One work item as the producer and the consumer see it.
+struct Item {
+    const uint8_t *base;  // time row 0, input 0 of the item's channel
+    int64_t t_stride;     // bytes between time rows
+    void *out;            // the channel's packed visibilities
+    int ninput, nb, item;
+};
+
+// Work source of a single array: flat id B -> channel f with B % 8 == f % 8,
+// so with round-robin dispatch over the 8 XCDs all items of a channel run on
+// one XCD and share its L2; padding ids of a channel count that is not a
+// multiple of 8 return false.
+struct SingleArray {
+    const uint8_t *in;
+    void *out;
+    int64_t t_stride;
+    int64_t out_chan_bytes;  // bytes of one channel's visibilities
+    int nchan, ninput, nitems, nb, bps;
+
+    __device__ __forceinline__ bool get(int B, Item &it) const {
+        const int s = B >> 3;
+        const int cl = s / nitems;
+        it.item = s - cl * nitems;
+        const int f = cl * 8 + (B & 7);
+        it.base = in + (int64_t)f * ninput * bps;
+        it.t_stride = t_stride;
+        it.out = (uint8_t *)out + (int64_t)f * out_chan_bytes;
+        it.ninput = ninput;
+        it.nb = nb;
+        return f < nchan;
+    }
+};
+
+// DMA producer: walks the same work sequence as the consumer, kRing-1 stages
+// ahead.  Per item it holds, for each of this lane's DMA instructions, the
+// byte offset of its chunk from the item's time-row base and (bit ii of
+// okmask) whether the chunk lies inside the array.
+struct Producer {
+    int B, ps, issued;
+    bool valid, straddle;
+    int okmask;
+    Item it;
+    int64_t d_off[kDmaPerWave];
+};
+
+// Geometry of DMA instruction ii of DMA wave dw: the stage row this lane
+// fetches, and the LDS slot and first input (within the slot) of its chunk.
+template <class F>
+__device__ __forceinline__ void dma_geom(int dw, int ii, int lane, int &row, int &slot, int &inp) {
+    row = (dw * kDmaPerWave + ii) * F::kRowsPerDma + lane / F::kChunks;
+    const int c = (lane % F::kChunks) ^ F::swz(row);
+    slot = c / F::kChunksPerSlot;
+    inp = (c % F::kChunksPerSlot) * F::kInputsPerChunk;
+}
+
+template <class F>
+__device__ __forceinline__ void prod_item(Producer &P, int dw, int lane) {
+    Task tk;
+    decode_item(P.it.nb, P.it.item, tk);
+    P.okmask = 0;
+#pragma unroll
+    for (int ii = 0; ii < kDmaPerWave; ++ii) {
+        int row, slot, inp0;
+        dma_geom<F>(dw, ii, lane, row, slot, inp0);
+        const int blk = pick4(tk.blk, slot);
+        const int inp = blk * kBlk + inp0;
+        const bool ok = blk >= 0 && inp < P.it.ninput;
+        P.okmask |= ok ? (1 << ii) : 0;
+        P.d_off[ii] = (int64_t)row * P.it.t_stride + (int64_t)inp * F::kBps;
+    }
+    // A chunk can run past ninput only in the block holding the last input,
+    // and only when ninput is not a multiple of the inputs per chunk.
+    const int last = (P.it.ninput - 1) / kBlk;
+    P.straddle = (P.it.ninput % F::kInputsPerChunk) != 0 &&
+                 (tk.blk[0] == last || tk.blk[1] == last || tk.blk[2] == last || tk.blk[3] == last);
+}
+
+template <class F, class W>
+__device__ __forceinline__ void prod_advance(Producer &P, const W &w, int total_flat, int grid,
+                                             int dw, int lane) {
+    P.valid = false;
+    while (P.B < total_flat && !(P.valid = w.get(P.B, P.it))) P.B += grid;
+    if (P.valid) prod_item<F>(P, dw, lane);
+}
+
+template <class F, class W>
+__device__ __forceinline__ void prod_issue(Producer &P, const W &w, int nt, int nst, int total_flat,
+                                           int grid, uint8_t *lds, uint32_t lds_base, int dw,
+                                           int lane) {
+    const uint8_t *zero = (const uint8_t *)&kZeroChunk;
+    const int slot = P.issued % kRing;
+    const uint32_t sbase = lds_base + slot * kStageBytes + dw * kDmaPerWave * 1024;
+    const int t0 = P.ps * F::kT;
+    const uint8_t *rowbase = P.it.base + (int64_t)t0 * P.it.t_stride;
+    if (!P.straddle && t0 + F::kT <= nt) {
+        // fast path: every row of the stage exists and no chunk straddles
+#pragma unroll
+        for (int ii = 0; ii < kDmaPerWave; ++ii)
+            dma16(((P.okmask >> ii) & 1) ? rowbase + P.d_off[ii] : zero, sbase + ii * 1024);
+    } else {
+#pragma unroll
+        for (int ii = 0; ii < kDmaPerWave; ++ii) {
+            int row, sl, inp0;
+            dma_geom<F>(dw, ii, lane, row, sl, inp0);
+            const int t = t0 + row;
+            const int inp = (int)((P.d_off[ii] - (int64_t)row * P.it.t_stride) / F::kBps);
+            const bool ok = ((P.okmask >> ii) & 1) && t < nt;
+            const bool straddle = ok && inp + F::kInputsPerChunk > P.it.ninput;
+            if (!straddle) dma16(ok ? rowbase + P.d_off[ii] : zero, sbase + ii * 1024);
+            if (straddle) {
+                // chunk runs past the last input: fetch whole 4-byte words
+                // (ninput % 4 == 0) and zero-fill the rest.
+                const uint8_t *p = rowbase + P.d_off[ii];
+                const int nwords = ((P.it.ninput - inp) * F::kBps) / 4;
+                uint32_t wd[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) wd[k] = k < nwords ? ((const uint32_t *)p)[k] : 0u;
+                uint8_t *l = lds + slot * kStageBytes + (dw * kDmaPerWave + ii) * 1024 + lane * 16;
+                *(uint4 *)l = uint4{wd[0], wd[1], wd[2], wd[3]};
+            }
+        }
+    }
+    ++P.issued;
+    if (++P.ps == nst) {
+        P.ps = 0;
+        P.B += grid;
+        prod_advance<F>(P, w, total_flat, grid, dw, lane);
+    }
+}
+
+// The persistent loop shared by every X-engine kernel.  F is the LDS row
+// format, C the consumer policy:
+//   C::Acc, C::Bases;  C::zero(acc);  C::bind(job, lane, bases);
+//   C::stage(stage_ptr, bases, acc);  C::epilogue(job, it, acc, lane, overwrite).
+// The stage loop: every wave waits for its own DMA of the stage, the barrier
+// publishes it, the slot read last is refilled, then the MFMA work of the
+// stage runs.  The vector-memory counter is in order for loads, but the
+// epilogue's stores share it and may complete out of order with them, so the
+// first wait after an epilogue (and the tail of the sequence) waits for
+// everything.
+template <class F, class C, class W>
+__device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int overwrite) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+    const int lane = tid & 63;
+    const int dw = wave;  // every wave issues kDmaPerWave of each stage's DMA
+    const int grid = gridDim.x;
+    const int nst = (nt + F::kT - 1) / F::kT;
+
+    // ---- consumer cursor (drives the loop of every wave)
+    int cB = blockIdx.x;
+    Item cit;
+    bool cvalid = false;
+    while (cB < total_flat && !(cvalid = w.get(cB, cit))) cB += grid;
+    if (!cvalid) return;  // no work for this workgroup
+
+    // ---- producer cursor (every wave issues its share of each stage)
+    Producer P;
+    P.B = blockIdx.x;
+    P.ps = 0;
+    P.issued = 0;
+    prod_advance<F>(P, w, total_flat, grid, dw, lane);
+
+    WaveJob job;
+    typename C::Bases fb;
+    {
+        Task tk;
+        decode_item(cit.nb, cit.item, tk);
+        job = make_job(tk, wave, cit.ninput);
+        C::bind(job, lane, fb);
+    }
+
+    typename C::Acc acc;
+    C::zero(acc);
+
+    for (int k = 0; k < kRing - 1 && P.valid; ++k)
+        prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+
+    int consumed = 0;
+    int cs = 0;
+    bool after_epilogue = false;
+    while (true) {
+        if (after_epilogue) wait_vm<0>();
+        else wait_stage(P.issued - consumed - 1);
+        block_barrier();
+        if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+
+        const uint8_t *stage = lds + (consumed % kRing) * kStageBytes;
+        if (job.active) C::stage(stage, fb, acc);
+        ++consumed;
+        after_epilogue = false;
+        if (++cs == nst) {
+            if (job.active) C::epilogue(job, cit, acc, lane, overwrite);
+            C::zero(acc);
+            cs = 0;
+            cvalid = false;
+            cB += grid;
+            while (cB < total_flat && !(cvalid = w.get(cB, cit))) cB += grid;
+            if (!cvalid) break;
+            Task tk;
+            decode_item(cit.nb, cit.item, tk);
+            job = make_job(tk, wave, cit.ninput);
+            C::bind(job, lane, fb);
+            after_epilogue = true;
+        }
+    }
+    wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
+}
+
+// Persistent grid: one workgroup per CU, a multiple of 8 (the XCD count) and
+// at most the number of flat ids.
+inline int64_t persistent_grid(int num_cus, int64_t total_flat) {
+    int64_t grid = (int64_t)(num_cus > 0 ? num_cus : 256) / 8 * 8;
+    if (grid < 8) grid = 8;
+    if (grid > total_flat) grid = total_flat;
+    return grid;
+}
+
+}  // namespace
+}  // namespace bfx

@@ -1,0 +1,215 @@
+// Binary16 X-engine for gfx950: cf16 voltages -> binary32 visibilities.
+//
+// Per channel f the kernel forms V = sum_t x_t x_t^H, lower triangle (the FX
+// correlator's cross-multiply, Sec. 2.2 linear-algebra module and Sec. 7),
+// with binary16 products and binary32 accumulation on MFMA.
+//
+// Formulation.  Each complex input i is two real rows of a matrix Y
+// (row 2i = Re x_i, row 2i+1 = Im x_i, columns = time), and the kernel forms
+// the real product C = Y Y^T on the lower block triangle.  Per complex pair
+//   Re V_ij = C[2i][2j] + C[2i+1][2j+1],   Im V_ij = C[2i+1][2j] - C[2i][2j+1],
+// which is exactly 4 real MACs per complex MAC: no redundant work.  The cf16
+// row [t][f][i] in memory, (re, im) interleaved, already is row t of Y^T, so
+// the LDS stage needs no de-interleave: ds_read_b64_tr_b16 turns 4 time rows
+// x 16 real rows into per-real-row K(time)-contiguous MFMA fragments.
+//
+// Tiles.  Work decomposition, LDS ring and persistent loop are those of the
+// integer kernels (xe_common.h); a stage holds 16 time rows of 256 complex
+// inputs = one K step of v_mfma_f32_32x32x16_f16.  A wave's tile is 64 complex
+// rows x 32 complex columns = 128 x 64 real: 4 x 2 sub-blocks of 32 x 32
+// binary32 accumulators (128 registers), 8 MFMAs per stage.
+//
+// Epilogue.  In the 32x32 MFMA output layout (lane l, register v hold real row
+// 8*(v/4) + 4*(l/32) + v%4, real column l%32) the four real products of a
+// complex pair sit in two adjacent registers of two adjacent lanes.  One DPP
+// lane swap per register pair brings them together: even lanes finish the
+// even complex row of each register quad, odd lanes the odd one, so every
+// lane stores.
+//
+// Accuracy.  binary16 x binary16 products are exact in binary32; the error is
+// the binary32 summation over T samples: |dV_ij| <= ~T u sum_t |x_i||x_j|
+// <= ~T u sqrt(V_ii V_jj) (u = 2^-24, Cauchy-Schwarz).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "bfx_internal.h"
+#include "xe_common.h"
+
+namespace bfx {
+namespace {
+
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+
+using F16Fmt = RowFmt<4>;  // 1 KiB rows, 16 rows per stage
+static_assert(F16Fmt::kT == 16, "one 16-sample MFMA step per stage");
+
+struct F16Acc {
+    v16f c[4][2];  // [row sub-block of 16 complex][column sub-block of 16 complex]
+};
+
+// Per-lane LDS byte offset (within a stage) of the first transposing read of
+// the fragment of complex inputs ioff..ioff+15 (real rows 2*ioff..2*ioff+31).
+// tr_b16: lanes 4r..4r+3 of a 16-lane group name the four 8-byte quarters of
+// time row r (r = 0..3); lane j receives 16-bit element j of rows 0..3.  Group
+// G covers real rows +16*(G&1) and times +8*(G>>1) (the MFMA K half).  The
+// swizzle only depends on t % 4, which is the same for the second read (4 rows
+// further), so that one is at a fixed distance.
+__device__ inline int frag_base16(int ioff, int lane) {
+    using F = F16Fmt;
+    const int G = (lane >> 4) & 3;
+    const int k = lane & 15;
+    const int t = 8 * (G >> 1) + (k >> 2);
+    const int byte = 4 * ioff + 32 * (G & 1) + 8 * (k & 3);
+    return t * F::kRow + 16 * ((byte >> 4) ^ F::swz(t)) + (byte & 15);
+}
+
+__device__ __forceinline__ v8h read_frag16(const uint8_t *p) {
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)p);
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p + 4 * F16Fmt::kRow));
+    const v4h l = __builtin_bit_cast(v4h, lo);
+    const v4h h = __builtin_bit_cast(v4h, hi);
+    return v8h{l[0], l[1], l[2], l[3], h[0], h[1], h[2], h[3]};
+}
+
+struct F16Consumer {
+    typedef F16Acc Acc;
+    struct Bases {
+        int fb[6];  // 4 row fragments, 2 column fragments
+    };
+    __device__ static __forceinline__ void zero(Acc &acc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc.c[r][c] = v16f{0.0f};
+    }
+    __device__ static __forceinline__ void bind(const WaveJob &job, int lane, Bases &b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b.fb[r] = frag_base16(job.rrow + 16 * r, lane);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) b.fb[4 + c] = frag_base16(job.crow + 16 * c, lane);
+    }
+    __device__ static __forceinline__ void stage(const uint8_t *st, const Bases &b, Acc &acc) {
+        // reads in the order the MFMAs below consume them
+        const v8h b0 = read_frag16(st + b.fb[4]);
+        const v8h a0 = read_frag16(st + b.fb[0]);
+        const v8h a1 = read_frag16(st + b.fb[1]);
+        const v8h b1 = read_frag16(st + b.fb[5]);
+        const v8h a2 = read_frag16(st + b.fb[2]);
+        const v8h a3 = read_frag16(st + b.fb[3]);
+        acc.c[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b0, acc.c[0][0], 0, 0, 0);
+        acc.c[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b0, acc.c[1][0], 0, 0, 0);
+        acc.c[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b1, acc.c[0][1], 0, 0, 0);
+        acc.c[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, acc.c[1][1], 0, 0, 0);
+        acc.c[2][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2, b0, acc.c[2][0], 0, 0, 0);
+        acc.c[2][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2, b1, acc.c[2][1], 0, 0, 0);
+        acc.c[3][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a3, b0, acc.c[3][0], 0, 0, 0);
+        acc.c[3][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a3, b1, acc.c[3][1], 0, 0, 0);
+    }
+
+    // Swap with the neighbouring lane (DPP quad_perm [1,0,3,2]).
+    __device__ static __forceinline__ float swap_lane(float x) {
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+    }
+
+    __device__ static __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc,
+                                                    int lane, int overwrite) {
+        const int ninput = it.ninput;
+        uint8_t *obase = (uint8_t *)it.out;
+        const int g = lane >> 5;
+        const int odd = lane & 1;
+        const int il = j.rblk * kBlk + 2 * g + odd;                  // row of d = 0
+        const int jl = j.cblk * kBlk + 32 * j.ch + ((lane & 31) >> 1);  // column of c = 0
+        const uint32_t base = (uint32_t)((il * (il + 1) / 2 + jl) * 8);
+        const uint32_t step = (uint32_t)(il * 8);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int R0 = j.rblk * kBlk + 16 * r;                // first complex row
+                const int C0 = j.cblk * kBlk + 32 * j.ch + 16 * c;    // first complex column
+                if (R0 + 15 < C0 || R0 >= ninput || C0 >= ninput) continue;  // dead sub-block
+                const bool interior = R0 >= C0 + 15 && R0 + 15 < ninput;
+                const v16f &v = acc.c[r][c];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float send0 = odd ? v[4 * s] : v[4 * s + 2];
+                    const float send1 = odd ? v[4 * s + 1] : v[4 * s + 3];
+                    const float keep0 = odd ? v[4 * s + 2] : v[4 * s];
+                    const float keep1 = odd ? v[4 * s + 3] : v[4 * s + 1];
+                    const float recv0 = swap_lane(send0);
+                    const float recv1 = swap_lane(send1);
+                    // even lane: Re = C[re][re] (keep0) + C[im][im] (recv1),
+                    //            Im = C[im][re] (keep1) - C[re][im] (recv0);
+                    // odd lane:  Re = C[re][re] (recv0) + C[im][im] (keep1),
+                    //            Im = C[im][re] (recv1) - C[re][im] (keep0).
+                    float vr = (odd ? recv0 : keep0) + (odd ? keep1 : recv1);
+                    float vi = (odd ? recv1 : keep1) - (odd ? keep0 : recv0);
+                    const int d = 16 * r + 4 * s;
+                    const int i = il + d;
+                    const int jj = jl + 16 * c;
+                    if (interior || (i < ninput && jj <= i)) {
+                        const uint32_t off = base + (uint32_t)(16 * c * 8) + (uint32_t)d * step +
+                                             (uint32_t)(d * (d + 1) / 2 * 8);
+                        float2 *dst = (float2 *)(obase + off);
+                        if (!overwrite) {
+                            const float2 old = *dst;
+                            vr += old.x;
+                            vi += old.y;
+                        }
+                        *dst = float2{vr, vi};
+                    }
+                }
+            }
+        }
+    }
+};
+
+__global__ __launch_bounds__(kThreads, 1) void xengine_f16_kernel(SingleArray w, int nt,
+                                                                  int total_flat, int overwrite) {
+    xe_loop<F16Fmt, F16Consumer>(w, nt, total_flat, overwrite);
+}
+
+int g_num_cus = 0;
+std::once_flag g_init_once;
+hipError_t g_init_err = hipSuccess;
+
+void init_once() {
+    int dev = 0;
+    g_init_err = hipGetDevice(&dev);
+    if (g_init_err != hipSuccess) return;
+    hipDeviceProp_t prop;
+    g_init_err = hipGetDeviceProperties(&prop, dev);
+    if (g_init_err != hipSuccess) return;
+    g_num_cus = prop.multiProcessorCount;
+    g_init_err = hipFuncSetAttribute((const void *)xengine_f16_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+}
+
+}  // namespace
+
+hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
+                              float *out, bool overwrite, hipStream_t s) {
+    std::call_once(g_init_once, init_once);
+    if (g_init_err != hipSuccess) return g_init_err;
+    SingleArray w;
+    w.in = (const uint8_t *)in;
+    w.out = out;
+    w.bps = 4;
+    w.t_stride = (int64_t)nchan * ninput * 4;
+    w.out_chan_bytes = (int64_t)ninput * (ninput + 1) / 2 * 8;
+    w.nchan = nchan;
+    w.ninput = ninput;
+    w.nb = (ninput + kBlk - 1) / kBlk;
+    w.nitems = tri_items(w.nb);
+    const int64_t total_flat = ((int64_t)nchan + 7) / 8 * 8 * w.nitems;
+    const int64_t grid = persistent_grid(g_num_cus, total_flat);
+    hipLaunchKernelGGL(xengine_f16_kernel, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, s, w,
+                       (int)nt, (int)total_flat, (int)overwrite);
+    return hipGetLastError();
+}
+
+}  // namespace bfx

@@ -29,3 +29,12 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def cf16_full():
+    """The 512-input, 2048-channel, 1024-sample cf16 voltage block (4.3 GB),
+    generated once per session for the full-size FP16 X-engine and
+    beamformer cases."""
+    import synth
+    return synth.cf16_voltages(5, 1024, 2048, 512)

@@ -128,6 +128,13 @@ def test_beamform_argument_errors(kw):
     assert ei.value.status == bfx.BFX_EINVAL
 
 
+@pytest.mark.parametrize("navg", [3, 64, 128])
+def test_beamform_unsupported_navg(navg):
+    with pytest.raises(bfx.BfxError) as ei:
+        bfx.bfx_beamform_detect(FAKE, FAKE, 64, 2, 4, 384, navg, FAKE, stream=0)
+    assert ei.value.status == bfx.BFX_ENOTSUP
+
+
 def test_batched_create_validation_host_side():
     with pytest.raises(bfx.BfxError) as ei:
         bfx.bfx_xengine_create_batched([32, 6], [4, 4], "ci8")
