@@ -70,6 +70,173 @@ def cpu_baseline(raw_gulp, budget_s=15.0):
                       f"({N_TIME} samples), int64 triple loop, {dt:.1f} s"}
 
 
+PEAK_FP16_TFLOPS = 2500.0  # MI355X dense FP16 MFMA
+PEAK_FP32_TFLOPS = 157.3   # FP32 vector
+PEAK_HBM_GBPS = 8000.0
+
+
+def time_launches(fn, reps, warm=2):
+    """Average / median / min duration (ms) of fn() over reps calls, each
+    bracketed by HIP events on torch's current stream (the launch stream)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    d = sorted(a.elapsed_time(b) for a, b in evs)
+    return sum(d) / len(d), d[len(d) // 2], d[0]
+
+
+def _row(kernel, workload, avg_ms, med_ms, work, work_unit, peak, peak_unit, bound, nbytes,
+         extra=None):
+    """One measured row: `work` per launch in units of `work_unit` (ops or
+    bytes), achieved rate against `peak` of the bound resource."""
+    if bound == "hbm":
+        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    else:
+        achieved = work / (avg_ms * 1e-3) / 1e12
+    r = {"kernel": kernel, "workload": workload, "bound": bound,
+         "avg_launch_us": round(avg_ms * 1e3, 2), "median_launch_us": round(med_ms * 1e3, 2),
+         "achieved": round(achieved, 2), "peak": peak, "unit": peak_unit,
+         "frac": round(achieved / peak, 4),
+         "algorithmic_" + work_unit + "_per_launch": work,
+         "algorithmic_hbm_bytes_per_launch": nbytes,
+         "hbm_GBps_algorithmic": round(nbytes / (avg_ms * 1e-3) / 1e9, 1)}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def row_fengine(reps):
+    """F-engine: 256 real int8 inputs x 512 frames of 4096 (ADC noise sigma 16
+    plus a unit tone at channel 777 with per-input delays), ci8 out."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    N, S, NFFT = 256, 512, 4096
+    g = torch.Generator(device="cuda").manual_seed(3)
+    t = torch.arange(S * NFFT, device="cuda", dtype=torch.float64)[:, None]
+    tau = torch.rand(1, N, device="cuda", dtype=torch.float64, generator=g) * 50.0
+    tone = torch.cos(2 * torch.pi * 777.0 * (t - tau) / NFFT)
+    x = torch.randn(S * NFFT, N, device="cuda", dtype=torch.float64, generator=g) * 16.0 + tone
+    x = torch.clamp(torch.round(x), -127, 127).to(torch.int8)
+    del t, tone
+    scale = torch.full((NFFT // 2,), 8.0 / (16.0 * (NFFT / 2) ** 0.5), device="cuda",
+                       dtype=torch.float32)
+    out = torch.empty(S * (NFFT // 2) * N * 2, dtype=torch.int8, device="cuda")
+    avg, med, _ = time_launches(lambda: bfx.bfx_fengine(x, N, NFFT, S, scale, out, out="ci8"), reps)
+    nbytes = S * NFFT * N + S * (NFFT // 2) * N * 2
+    flops = int(2.5 * NFFT * 12) * S * N
+    r = _row("fengine_kernel<ci8>", "256 inputs x 512 frames x 4096-point real FFT -> ci8",
+             avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
+             {"fft_flops_per_launch": flops,
+              "fp32_alu_frac": round(flops / (avg * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+              "msamples_per_s": round(S * NFFT * N / (avg * 1e-3) / 1e6, 1)})
+    del x, out
+    return r
+
+
+def _cf16_block(T, F, N, seed):
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    return torch.randn(T * F * N * 2, device="cuda", dtype=torch.float32, generator=g).to(torch.float16)
+
+
+def row_xengine_f16(reps, x=None):
+    """FP16 X-engine: 512 inputs, 2048 channels, 1024 samples cf16 N(0,1)."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    T, F, N = 1024, 2048, 512
+    x = _cf16_block(T, F, N, 5) if x is None else x
+    plan = bfx.bfx_xengine_create(N, F, "cf16")
+    acc = bfx.visibilities_buffer(plan)
+    avg, med, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(plan, x, T, acc, overwrite=True), reps)
+    cmac = F * T * N * (N + 1) // 2
+    nbytes = T * F * N * 4 + F * N * (N + 1) // 2 * 8
+    r = _row("xengine_f16_kernel", "512 inputs x 2048 channels x 1024 samples, cf16 -> cf32",
+             avg, med, 8 * cmac, "flops", PEAK_FP16_TFLOPS, "TFLOP/s", "mfma", nbytes,
+             {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
+              "hbm_frac_algorithmic": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)})
+    # FP64 running sum of the binary32 dump (row a5, floating-point path)
+    run64 = torch.zeros(acc.numel(), dtype=torch.float64, device="cuda")
+    davg, dmed, _ = time_launches(lambda: bfx.bfx_xengine_dump(plan, acc, None, run64), max(3, reps // 2))
+    dbytes = acc.numel() * 4 + run64.numel() * 16
+    d = _row("dump_kernel<float> (FP64 running sum)", "2048 x 131328 cf32 visibilities",
+             davg, dmed, dbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", dbytes)
+    plan.close()
+    del acc, run64
+    return r, d, x
+
+
+def row_beamform(reps, x=None):
+    """Beamformer: 512 inputs, 2048 channels, 32 beams, 1024 samples, navg 16."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    T, F, N, B, NAVG = 1024, 2048, 512, 32, 16
+    x = _cf16_block(T, F, N, 5) if x is None else x
+    g = torch.Generator(device="cuda").manual_seed(6)
+    th = torch.rand(F * B * N, device="cuda", dtype=torch.float64, generator=g) * (2 * torch.pi)
+    w = torch.stack([torch.cos(th), torch.sin(th)], dim=-1).to(torch.float16).reshape(-1)
+    del th
+    out = torch.empty(B * F * (T // NAVG), dtype=torch.float32, device="cuda")
+    avg, med, _ = time_launches(lambda: bfx.bfx_beamform_detect(x, w, N, F, B, T, NAVG, out), reps)
+    cmac = B * F * T * N
+    nbytes = T * F * N * 4 + F * B * N * 4 + out.numel() * 4
+    r = _row("beamform_kernel<4>", "512 inputs x 2048 channels x 1024 samples, 32 beams, navg 16",
+             avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
+             {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
+              "fp16_mfma_frac": round(8 * cmac / (avg * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4)})
+    del w, out
+    return r
+
+
+def row_batched(reps):
+    """Batched: 8 subarrays (32..512 inputs, 1024..64 channels), ci8, 256
+    samples, one persistent launch; also each subarray alone for comparison."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    T = 256
+    Ns = (32, 64, 96, 128, 192, 256, 384, 512)
+    Fs = (1024, 512, 512, 256, 256, 128, 128, 64)
+    plan = bfx.bfx_xengine_create_batched(Ns, Fs, "ci8")
+    g = torch.Generator(device="cuda").manual_seed(40)
+    nin = bfx.bfx_xengine_in_bytes(plan, T)
+    arena = torch.clamp(torch.round(torch.randn(nin, device="cuda", generator=g) * 8.0),
+                        -127, 127).to(torch.int8)
+    acc = bfx.visibilities_buffer(plan)
+    avg, med, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(plan, arena, T, acc, overwrite=True), reps)
+    cmac = sum(F * T * N * (N + 1) // 2 for N, F in zip(Ns, Fs))
+    nbytes = sum(T * F * N * 2 + F * N * (N + 1) // 2 * 8 for N, F in zip(Ns, Fs))
+    # each subarray alone: standalone HBM-roofline fractions
+    alone = []
+    for N, F in zip(Ns, Fs):
+        p1 = bfx.bfx_xengine_create(N, F, "ci8")
+        a1 = bfx.visibilities_buffer(p1)
+        x1 = arena[:T * F * N * 2]
+        a_avg, _, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(p1, x1, T, a1, overwrite=True), reps)
+        b1 = T * F * N * 2 + F * N * (N + 1) // 2 * 8
+        alone.append({"ninput": N, "nchan": F, "avg_launch_us": round(a_avg * 1e3, 2),
+                      "hbm_frac": round(b1 / (a_avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                      "tcmac_per_s": round(F * T * N * (N + 1) // 2 / (a_avg * 1e-3) / 1e12, 2)})
+        p1.close()
+    best = max(a["hbm_frac"] for a in alone)
+    frac = nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS
+    r = _row("xengine_batched_kernel<ci8>", "8 subarrays (32..512 inputs), ci8, 256 samples",
+             avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
+             {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
+              "sum_standalone_us": round(sum(a["avg_launch_us"] for a in alone), 2),
+              "best_standalone_hbm_frac": best,
+              "batched_over_best_standalone": round(frac / best, 4),
+              "standalone": alone})
+    plan.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +248,11 @@ def main():
                     help="only run this many X-engine launches on one gulp (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the other hot-path rows (F-engine, FP16 X, beamformer, batched)")
+    ap.add_argument("--row-reps", type=int, default=20)
+    ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "batched"],
+                    help="only time one row (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the X-engine "
@@ -107,6 +279,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 1 << 30}), flush=True)
+        return
+    if args.only_row:
+        fn = {"fengine": row_fengine, "xf16": lambda r: row_xengine_f16(r)[0],
+              "beamform": row_beamform, "batched": row_batched}[args.only_row]
+        print(json.dumps(fn(args.row_reps)), flush=True)
         return
     if args.profile_launches:
         raw = synth.voltages(2, N_TIME, N_CHAN, N_INPUT, "ci4", 2.5, 7, gulp=0)
@@ -196,6 +373,20 @@ def main():
         "hbm_GBps_algorithmic": round((gulp_bytes + out_bytes) / (avg_ms * 1e-3) / 1e9, 1),
     }
 
+    rows = None
+    if not args.no_rows:
+        rows = {}
+        print("[bench] row: F-engine", file=sys.stderr, flush=True)
+        rows["fengine"] = row_fengine(args.row_reps)
+        print("[bench] row: FP16 X-engine + FP64 running sum", file=sys.stderr, flush=True)
+        rows["xengine_f16"], rows["dump_run64"], x16 = row_xengine_f16(max(5, args.row_reps // 2))
+        print("[bench] row: beamformer", file=sys.stderr, flush=True)
+        rows["beamform"] = row_beamform(args.row_reps, x16)
+        del x16
+        print("[bench] row: batched", file=sys.stderr, flush=True)
+        rows["batched"] = row_batched(args.row_reps)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -224,6 +415,7 @@ def main():
         "input_GBps": round(in_gbs, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "rows": rows,
     }
     print(json.dumps(line), flush=True)
     plan.close()

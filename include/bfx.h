@@ -1,8 +1,9 @@
 /*
  * bfx.h -- C ABI of an MI355X (gfx950) FX-correlator hot path.
  *
- * The calls follow the gulp model of the Bifrost paper (Sec. 3.1: a block
- * reads a ring buffer one "gulp" at a time; the ring defaults to four gulps):
+ * The calls follow the gulp model of the Bifrost paper (Sec. 3.5: a block
+ * reads a ring buffer one "gulp" at a time; a ring holds four gulps by
+ * default):
  * each call consumes one gulp that already sits in caller-owned device memory
  * and enqueues its work on the caller's HIP stream.
  *

@@ -32,7 +32,6 @@ bfx_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Defined with the kernels.
-int xengine_tri_items(int32_t ninput);
 hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               float *out, bool overwrite, hipStream_t s);
 hipError_t launch_dump(bool is_int, const void *acc, void *out, double *run64, int64_t n,
@@ -107,24 +106,37 @@ void offsets(const bfx_xengine *p, int32_t k, int64_t ntime, int64_t *in_off, in
 
 // Work list of a batched plan.  Every work item costs the same (a fixed
 // number of LDS stages, whatever its tile count), so balance is by item
-// count: channels, largest first, go whole to the least loaded of 8 queues
-// (one per XCD, so a channel's items share an L2 and run side by side); the
-// queues are padded to equal length and interleaved (entry 8q + x = item q of
-// queue x).
+// count.  A work group is one channel (all its triangle items) or, for a
+// one-block subarray, up to four channels packed into one item.  Groups,
+// largest first, go whole to the least loaded of 8 queues (one per XCD, so a
+// channel's items share an L2 and run side by side); the queues are padded to
+// equal length and interleaved (entry 8q + x = item q of queue x).
 std::vector<int2> build_work(const std::vector<BatchUnit> &units) {
-    struct Chan { int32_t k, f, n; };
-    std::vector<Chan> chans;
-    for (int32_t k = 0; k < (int32_t)units.size(); ++k)
-        for (int32_t f = 0; f < units[k].nchan; ++f) chans.push_back(Chan{k, f, units[k].nitems});
-    std::stable_sort(chans.begin(), chans.end(),
-                     [](const Chan &a, const Chan &b) { return a.n > b.n; });
+    struct Group { int32_t k, f0, n; bool packed; };
+    std::vector<Group> groups;
+    for (int32_t k = 0; k < (int32_t)units.size(); ++k) {
+        const BatchUnit &u = units[k];
+        if (u.nb == 1) {
+            for (int32_t f = 0; f < u.nchan; f += 4)
+                groups.push_back(Group{k, f, u.nchan - f < 4 ? u.nchan - f : 4, true});
+        } else {
+            for (int32_t f = 0; f < u.nchan; ++f) groups.push_back(Group{k, f, u.nitems, false});
+        }
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) {
+        return (a.packed ? 1 : a.n) > (b.packed ? 1 : b.n);
+    });
     std::vector<int2> q[8];
-    for (const Chan &c : chans) {
+    for (const Group &g : groups) {
         int best = 0;
         for (int x = 1; x < 8; ++x)
             if (q[x].size() < q[best].size()) best = x;
-        for (int32_t it = 0; it < c.n; ++it)
-            q[best].push_back(int2{c.k | (it << kBatchSubBits), c.f});
+        if (g.packed) {
+            q[best].push_back(int2{g.k | (g.n << kBatchSubBits) | kBatchPacked, g.f0});
+        } else {
+            for (int32_t it = 0; it < g.n; ++it)
+                q[best].push_back(int2{g.k | (it << kBatchSubBits), g.f0});
+        }
     }
     size_t len = 0;
     for (int x = 0; x < 8; ++x) len = q[x].size() > len ? q[x].size() : len;
@@ -195,7 +207,7 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
     for (int32_t k = 0; k < nsub; ++k) {
         bfx_status st = check_dims(ninput[k], nchan[k]);
         if (st != BFX_OK) return st;
-        nwork += (int64_t)nchan[k] * xengine_tri_items(ninput[k]);
+        nwork += xengine_items(ninput[k], nchan[k]);
     }
     if (nwork > (int64_t)1 << 24)
         return fail(BFX_EINVAL, "batched plan has %lld work items (limit 2^24)", (long long)nwork);
@@ -218,7 +230,7 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
         u.nchan = nchan[k];
         u.ninput = ninput[k];
         u.nb = (ninput[k] + 63) / 64;
-        u.nitems = xengine_tri_items(ninput[k]);
+        u.nitems = (int32_t)(xengine_items(ninput[k], 1));  // per channel (1 when packed)
     }
     const std::vector<int2> work = build_work(units);
     p->nwork = (int64_t)work.size();

@@ -37,9 +37,16 @@ struct BatchUnit {
     int32_t nb;          // input blocks of 64
 };
 
-// Work-list entry of a batched launch: x = subarray | item << 12 (x < 0: a
-// padding entry), y = channel.
+// Work-list entry of a batched launch: x = subarray | field << 12, y = first
+// channel; field = triangle item of channel y, or, with kBatchPacked set, the
+// number (1..4) of channels y, y+1, ... of a one-block subarray packed into
+// one item.  x < 0: a padding entry.
 constexpr int kBatchSubBits = 12;
+constexpr int kBatchPacked = 1 << 30;
+
+// Work items of one array: channels x triangle items, or groups of four
+// channels when the array has a single 64-input block.
+int64_t xengine_items(int32_t ninput, int32_t nchan);
 
 // Integer X-engine over a batched plan: `nwork` work-list entries (a multiple
 // of 8; entry B runs on XCD B % 8), time rows [t0, t0 + nt) of every

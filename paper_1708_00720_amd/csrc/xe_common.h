@@ -43,7 +43,11 @@ constexpr int kDmaWaves = kWaves; // every wave issues part of each stage's DMA
 constexpr int kThreads = 64 * kWaves;
 constexpr int kStageBytes = 16384;
 constexpr int kRing = 8;          // LDS stages in flight (128 KiB)
-constexpr int kLdsBytes = kRing * kStageBytes;
+constexpr int kRingBytes = kRing * kStageBytes;
+// The ring plus 1 KiB that receives the dummy DMA of a chunk fetched by the
+// synchronous path (keeps every stage at exactly kDmaPerWave DMA operations
+// per wave, which the vmcnt waits count on).
+constexpr int kLdsBytes = kRingBytes + 1024;
 constexpr int kDmaPerWave = kStageBytes / 1024 / kDmaWaves;  // 16-byte-per-lane DMA instructions
 
 // Layout of one LDS stage: kT time rows of 256 inputs of BPS bytes each
@@ -66,9 +70,10 @@ struct RowFmt {
 };
 
 struct Task {
-    int blk[kSlots];  // input block held by each LDS slot, -1 = unused
-    int rs[4];        // per block pair: LDS slot of its row block, -1 = unused
-    int cs[4];        // per block pair: LDS slot of its column block
+    int blk[kSlots];   // input block held by each LDS slot, -1 = unused
+    int chan[kSlots];  // channel of each LDS slot, relative to the item's first
+    int rs[4];         // per block pair: LDS slot of its row block, -1 = unused
+    int cs[4];         // per block pair: LDS slot of its column block
 };
 
 __host__ __device__ inline int tri_items(int nb) {
@@ -83,7 +88,7 @@ __device__ inline void decode_item(int nb, int item, Task &tk) {
     const int h = nb / 2;
     const int S = h * (h + 1) / 2;
     const bool odd = nb & 1;
-    for (int k = 0; k < 4; ++k) { tk.blk[k] = -1; tk.rs[k] = -1; tk.cs[k] = -1; }
+    for (int k = 0; k < 4; ++k) { tk.blk[k] = -1; tk.chan[k] = 0; tk.rs[k] = -1; tk.cs[k] = -1; }
     if (item < S) {
         int a = (int)((sqrtf(8.0f * item + 1.0f) - 1.0f) * 0.5f);
         while ((a + 1) * (a + 2) / 2 <= item) ++a;
@@ -110,6 +115,19 @@ __device__ inline void decode_item(int nb, int item, Task &tk) {
             if (k < h) { tk.blk[w + 1] = 2 * k + 1; tk.rs[w] = 0; tk.cs[w] = w + 1; }
         }
         if (g == 0) { tk.rs[3] = 0; tk.cs[3] = 0; }
+    }
+}
+
+// A packed item: npack (1..4) channels of a one-block array (<= 64 inputs),
+// channel k in LDS slot k, block pairs (k, k) -- so small arrays fill all four
+// pair slots of a work item instead of one.
+__device__ inline void decode_packed(int npack, Task &tk) {
+    for (int k = 0; k < 4; ++k) {
+        const bool on = k < npack;
+        tk.blk[k] = on ? 0 : -1;
+        tk.chan[k] = k;
+        tk.rs[k] = on ? k : -1;
+        tk.cs[k] = on ? k : -1;
     }
 }
 
@@ -172,6 +190,7 @@ constexpr int kSchedMfma = 0x8;
 // w % 4 of the item, column half w / 4 (the two waves of a pair share a SIMD).
 struct WaveJob {
     int rblk, cblk, ch;
+    int ochan;       // channel of the pair, relative to the item's first
     int rrow, crow;  // LDS input offsets of the row block and of this wave's column half
     bool active, diag, full;
     unsigned live;   // bit r: sub-block (row half r, this column half) is needed
@@ -186,6 +205,7 @@ __device__ inline WaveJob make_job(const Task &tk, int wave, int ninput) {
     j.active = rs >= 0;
     j.rblk = j.active ? pick4(tk.blk, rs) : 0;
     j.cblk = j.active ? pick4(tk.blk, cs) : 0;
+    j.ochan = j.active ? pick4(tk.chan, rs) : 0;
     j.rrow = (rs < 0 ? 0 : rs) * kBlk;
     j.crow = (cs < 0 ? 0 : cs) * kBlk + 32 * j.ch;
     j.diag = j.active && rs == cs;
@@ -204,34 +224,49 @@ __device__ inline WaveJob make_job(const Task &tk, int wave, int ninput) {
 
 // One work item as the producer and the consumer see it.
 struct Item {
-    const uint8_t *base;  // time row 0, input 0 of the item's channel
-    int64_t t_stride;     // bytes between time rows
-    void *out;            // the channel's packed visibilities
+    const uint8_t *base;     // time row 0, input 0 of the item's (first) channel
+    int64_t t_stride;        // bytes between time rows
+    int64_t chan_bytes;      // bytes of one channel in a time row (ninput * sample bytes)
+    int64_t out_chan_bytes;  // bytes of one channel's packed visibilities
+    void *out;               // the (first) channel's visibilities
     int ninput, nb, item;
+    int npack;               // 0: triangle item `item` of one channel; 1..4: packed item
 };
 
-// Work source of a single array: flat id B -> channel f with B % 8 == f % 8,
-// so with round-robin dispatch over the 8 XCDs all items of a channel run on
-// one XCD and share its L2; padding ids of a channel count that is not a
-// multiple of 8 return false.
+__device__ inline void decode_task(const Item &it, Task &tk) {
+    if (it.npack) decode_packed(it.npack, tk);
+    else decode_item(it.nb, it.item, tk);
+}
+
+// Work source of a single array.  Flat id B maps to channel group g with
+// B % 8 == g % 8, so with round-robin dispatch over the 8 XCDs all items of a
+// channel run on one XCD and share its L2.  A group is one channel, or four
+// channels packed into one item when the array has a single input block.
+// Padding ids of a group count that is not a multiple of 8 return false.
 struct SingleArray {
     const uint8_t *in;
     void *out;
     int64_t t_stride;
     int64_t out_chan_bytes;  // bytes of one channel's visibilities
     int nchan, ninput, nitems, nb, bps;
+    int npk;      // channels per group: 4 when nb == 1, else 1
+    int ngroups;  // ceil(nchan / npk)
 
     __device__ __forceinline__ bool get(int B, Item &it) const {
         const int s = B >> 3;
         const int cl = s / nitems;
         it.item = s - cl * nitems;
-        const int f = cl * 8 + (B & 7);
-        it.base = in + (int64_t)f * ninput * bps;
+        const int g = cl * 8 + (B & 7);
+        const int f0 = g * npk;
+        it.npack = npk > 1 ? min(npk, nchan - f0) : 0;
+        it.chan_bytes = (int64_t)ninput * bps;
+        it.base = in + (int64_t)f0 * it.chan_bytes;
         it.t_stride = t_stride;
-        it.out = (uint8_t *)out + (int64_t)f * out_chan_bytes;
+        it.out_chan_bytes = out_chan_bytes;
+        it.out = (uint8_t *)out + (int64_t)f0 * out_chan_bytes;
         it.ninput = ninput;
         it.nb = nb;
-        return f < nchan;
+        return g < ngroups;
     }
 };
 
@@ -245,6 +280,7 @@ struct Producer {
     int okmask;
     Item it;
     int64_t d_off[kDmaPerWave];
+    int inp[kDmaPerWave];  // first input of each chunk within its channel
 };
 
 // Geometry of DMA instruction ii of DMA wave dw: the stage row this lane
@@ -260,7 +296,7 @@ __device__ __forceinline__ void dma_geom(int dw, int ii, int lane, int &row, int
 template <class F>
 __device__ __forceinline__ void prod_item(Producer &P, int dw, int lane) {
     Task tk;
-    decode_item(P.it.nb, P.it.item, tk);
+    decode_task(P.it, tk);
     P.okmask = 0;
 #pragma unroll
     for (int ii = 0; ii < kDmaPerWave; ++ii) {
@@ -270,7 +306,9 @@ __device__ __forceinline__ void prod_item(Producer &P, int dw, int lane) {
         const int inp = blk * kBlk + inp0;
         const bool ok = blk >= 0 && inp < P.it.ninput;
         P.okmask |= ok ? (1 << ii) : 0;
-        P.d_off[ii] = (int64_t)row * P.it.t_stride + (int64_t)inp * F::kBps;
+        P.d_off[ii] = (int64_t)row * P.it.t_stride + (int64_t)pick4(tk.chan, slot) * P.it.chan_bytes +
+                      (int64_t)inp * F::kBps;
+        P.inp[ii] = inp;
     }
     // A chunk can run past ninput only in the block holding the last input,
     // and only when ninput is not a multiple of the inputs per chunk.
@@ -307,13 +345,15 @@ __device__ __forceinline__ void prod_issue(Producer &P, const W &w, int nt, int 
             int row, sl, inp0;
             dma_geom<F>(dw, ii, lane, row, sl, inp0);
             const int t = t0 + row;
-            const int inp = (int)((P.d_off[ii] - (int64_t)row * P.it.t_stride) / F::kBps);
+            const int inp = P.inp[ii];
             const bool ok = ((P.okmask >> ii) & 1) && t < nt;
             const bool straddle = ok && inp + F::kInputsPerChunk > P.it.ninput;
             if (!straddle) dma16(ok ? rowbase + P.d_off[ii] : zero, sbase + ii * 1024);
             if (straddle) {
                 // chunk runs past the last input: fetch whole 4-byte words
-                // (ninput % 4 == 0) and zero-fill the rest.
+                // (ninput % 4 == 0) and zero-fill the rest; a DMA of the zero
+                // chunk into the spare kilobyte keeps the per-stage count.
+                dma16(zero, lds_base + kRingBytes);
                 const uint8_t *p = rowbase + P.d_off[ii];
                 const int nwords = ((P.it.ninput - inp) * F::kBps) / 4;
                 uint32_t wd[4];
@@ -332,16 +372,25 @@ __device__ __forceinline__ void prod_issue(Producer &P, const W &w, int nt, int 
     }
 }
 
-// The persistent loop shared by every X-engine kernel.  F is the LDS row
-// format, C the consumer policy:
-//   C::Acc, C::Bases;  C::zero(acc);  C::bind(job, lane, bases);
-//   C::stage(stage_ptr, bases, acc);  C::epilogue(job, it, acc, lane, overwrite).
-// The stage loop: every wave waits for its own DMA of the stage, the barrier
-// publishes it, the slot read last is refilled, then the MFMA work of the
-// stage runs.  The vector-memory counter is in order for loads, but the
-// epilogue's stores share it and may complete out of order with them, so the
-// first wait after an epilogue (and the tail of the sequence) waits for
-// everything.
+// Wait until this wave's LDS reads have returned (lgkmcnt = 0; vmcnt and
+// expcnt left at their maxima).
+__device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// The persistent loop shared by every X-engine kernel, software-pipelined
+// across stages.  F is the LDS row format, C the consumer policy:
+//   C::Acc, C::Raw, C::Bases;  C::zero(acc);  C::bind(job, lane, bases);
+//   C::read(stage_ptr, bases, raw)   -- issue the stage's transposing LDS reads;
+//   C::compute(raw, acc)             -- the stage's MFMA work from registers;
+//   C::epilogue(job, it, acc, lane, overwrite).
+// Iteration s: every wave waits for its own DMA of stage s+1, the barrier
+// publishes it, the ring slot of stage s (read completely by every wave before
+// the barrier) is refilled, the reads of stage s+1 are issued, and only then
+// do the MFMAs of stage s run -- so the LDS reads of one stage overlap the
+// matrix work of the previous one.  At an item's last stage the next item's
+// job is decoded first, so its first stage is read under the same overlap.
+// The vector-memory counter is in order for loads, but the epilogue's stores
+// share it and may complete out of order with them, so the first wait after
+// an epilogue (and the tail of the sequence) waits for everything.
 template <class F, class C, class W>
 __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int overwrite) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -372,44 +421,73 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     typename C::Bases fb;
     {
         Task tk;
-        decode_item(cit.nb, cit.item, tk);
+        decode_task(cit, tk);
         job = make_job(tk, wave, cit.ninput);
         C::bind(job, lane, fb);
     }
 
     typename C::Acc acc;
     C::zero(acc);
+    typename C::Raw ra, rb;
 
     for (int k = 0; k < kRing - 1 && P.valid; ++k)
         prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    wait_stage(P.issued - 1);
+    block_barrier();
+    if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    if (job.active) C::read(lds, fb, ra);
+    // Returned before the loop: the compiler's wait tracking merges the
+    // entry and back-edge states at the loop header, and reads still pending
+    // from the entry would make it wait for the next stage's reads as well
+    // before the current stage's MFMAs.
+    wait_lds();
 
-    int consumed = 0;
-    int cs = 0;
+    int s = 0;   // stage whose MFMA work this iteration does
+    int cs = 0;  // its index within the current item
     bool after_epilogue = false;
     while (true) {
-        if (after_epilogue) wait_vm<0>();
-        else wait_stage(P.issued - consumed - 1);
-        block_barrier();
-        if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-
-        const uint8_t *stage = lds + (consumed % kRing) * kStageBytes;
-        if (job.active) C::stage(stage, fb, acc);
-        ++consumed;
+        const bool last = cs + 1 == nst;
+        WaveJob njob = job;
+        typename C::Bases nfb = fb;
+        Item nit = cit;
+        bool more = true;
+        if (last) {
+            cB += grid;
+            more = false;
+            while (cB < total_flat && !(more = w.get(cB, nit))) cB += grid;
+            if (more) {
+                Task tk;
+                decode_task(nit, tk);
+                njob = make_job(tk, wave, nit.ninput);
+                C::bind(njob, lane, nfb);
+            }
+        }
+        if (more) {
+            // every read of stage s has returned: its slot may be refilled
+            wait_lds();
+            if (after_epilogue) wait_vm<0>();
+            else wait_stage(P.issued - (s + 1) - 1);
+            block_barrier();
+            if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+            if (njob.active) C::read(lds + ((s + 1) % kRing) * kStageBytes, nfb, rb);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // the reads above go out before the MFMAs below
         after_epilogue = false;
-        if (++cs == nst) {
+        if (job.active) C::compute(ra, acc);
+        if (last) {
             if (job.active) C::epilogue(job, cit, acc, lane, overwrite);
             C::zero(acc);
+            if (!more) break;
+            job = njob;
+            fb = nfb;
+            cit = nit;
             cs = 0;
-            cvalid = false;
-            cB += grid;
-            while (cB < total_flat && !(cvalid = w.get(cB, cit))) cB += grid;
-            if (!cvalid) break;
-            Task tk;
-            decode_item(cit.nb, cit.item, tk);
-            job = make_job(tk, wave, cit.ninput);
-            C::bind(job, lane, fb);
             after_epilogue = true;
+        } else {
+            ++cs;
         }
+        ra = rb;
+        ++s;
     }
     wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
 }

@@ -76,6 +76,9 @@ __device__ __forceinline__ v8h read_frag16(const uint8_t *p) {
 
 struct F16Consumer {
     typedef F16Acc Acc;
+    struct Raw {
+        v8h a[4], b[2];  // row and column fragments of one stage
+    };
     struct Bases {
         int fb[6];  // 4 row fragments, 2 column fragments
     };
@@ -91,22 +94,18 @@ struct F16Consumer {
 #pragma unroll
         for (int c = 0; c < 2; ++c) b.fb[4 + c] = frag_base16(job.crow + 16 * c, lane);
     }
-    __device__ static __forceinline__ void stage(const uint8_t *st, const Bases &b, Acc &acc) {
-        // reads in the order the MFMAs below consume them
-        const v8h b0 = read_frag16(st + b.fb[4]);
-        const v8h a0 = read_frag16(st + b.fb[0]);
-        const v8h a1 = read_frag16(st + b.fb[1]);
-        const v8h b1 = read_frag16(st + b.fb[5]);
-        const v8h a2 = read_frag16(st + b.fb[2]);
-        const v8h a3 = read_frag16(st + b.fb[3]);
-        acc.c[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b0, acc.c[0][0], 0, 0, 0);
-        acc.c[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b0, acc.c[1][0], 0, 0, 0);
-        acc.c[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b1, acc.c[0][1], 0, 0, 0);
-        acc.c[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, acc.c[1][1], 0, 0, 0);
-        acc.c[2][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2, b0, acc.c[2][0], 0, 0, 0);
-        acc.c[2][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2, b1, acc.c[2][1], 0, 0, 0);
-        acc.c[3][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a3, b0, acc.c[3][0], 0, 0, 0);
-        acc.c[3][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a3, b1, acc.c[3][1], 0, 0, 0);
+    __device__ static __forceinline__ void read(const uint8_t *st, const Bases &b, Raw &raw) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) raw.a[r] = read_frag16(st + b.fb[r]);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) raw.b[c] = read_frag16(st + b.fb[4 + c]);
+    }
+    __device__ static __forceinline__ void compute(const Raw &raw, Acc &acc) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc.c[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(raw.a[r], raw.b[c], acc.c[r][c], 0, 0, 0);
     }
 
     // Swap with the neighbouring lane (DPP quad_perm [1,0,3,2]).
@@ -118,7 +117,7 @@ struct F16Consumer {
     __device__ static __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc,
                                                     int lane, int overwrite) {
         const int ninput = it.ninput;
-        uint8_t *obase = (uint8_t *)it.out;
+        uint8_t *obase = (uint8_t *)it.out + (int64_t)j.ochan * it.out_chan_bytes;
         const int g = lane >> 5;
         const int odd = lane & 1;
         const int il = j.rblk * kBlk + 2 * g + odd;                  // row of d = 0
@@ -205,7 +204,9 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     w.ninput = ninput;
     w.nb = (ninput + kBlk - 1) / kBlk;
     w.nitems = tri_items(w.nb);
-    const int64_t total_flat = ((int64_t)nchan + 7) / 8 * 8 * w.nitems;
+    w.npk = w.nb == 1 ? 4 : 1;
+    w.ngroups = (nchan + w.npk - 1) / w.npk;
+    const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
     hipLaunchKernelGGL(xengine_f16_kernel, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, s, w,
                        (int)nt, (int)total_flat, (int)overwrite);

@@ -138,30 +138,38 @@ __device__ __forceinline__ void mfma8(const Frag &a0, const Frag &a1, const Frag
     acc.re[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.im, acc.re[1], 0, 0, 0);
 }
 
-// One stage of a wave's 64x32 tile.  All transposing reads of the stage are
-// issued first (one LDS latency per stage instead of one per fragment); the
-// split of the next 32-sample step is interleaved with the MFMAs of the
-// current one.  Every MFMA is unconditional (a dead sub-block of a diagonal
-// or ragged pair is computed and simply not stored): conditional MFMAs force
-// accumulator copies at every merge point.
+// Raw transposing reads of one stage of a wave's 64x32 tile: per 32-sample
+// step the two row fragments and the column fragment.
 template <bool CI4>
-__device__ __forceinline__ void mfma_stage(const uint8_t *stage, const int (&fb)[3], Acc &acc) {
+struct StageRaw {
+    RawFrag<CI4> r[Fmt<CI4>::kKK][3];
+};
+
+template <bool CI4>
+__device__ __forceinline__ void read_stage(const uint8_t *stage, const int (&fb)[3], StageRaw<CI4> &raw) {
+#pragma unroll
+    for (int kk = 0; kk < Fmt<CI4>::kKK; ++kk)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) raw.r[kk][f] = read_frag<CI4>(stage + fb[f], kk);
+}
+
+// MFMA work of one stage from registers.  The split of the next 32-sample step
+// is interleaved with the MFMAs of the current one.  Every MFMA is
+// unconditional (a dead sub-block of a diagonal or ragged pair is computed and
+// simply not stored): conditional MFMAs force accumulator copies at every
+// merge point.
+template <bool CI4>
+__device__ __forceinline__ void mfma_stage(const StageRaw<CI4> &raw, Acc &acc) {
     constexpr int KK = Fmt<CI4>::kKK;
-    RawFrag<CI4> raw[KK][3];
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-        for (int f = 0; f < 3; ++f) raw[kk][f] = read_frag<CI4>(stage + fb[f], kk);
-    __builtin_amdgcn_sched_barrier(0);  // keep every read ahead of the arithmetic
     Frag cur[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) cur[f] = split_frag<CI4>(raw[0][f]);
+    for (int f = 0; f < 3; ++f) cur[f] = split_frag<CI4>(raw.r[0][f]);
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
         Frag nxt[3];
         if (kk + 1 < KK) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f) nxt[f] = split_frag<CI4>(raw[kk + 1][f]);
+            for (int f = 0; f < 3; ++f) nxt[f] = split_frag<CI4>(raw.r[kk + 1][f]);
         }
         mfma8(cur[0], cur[1], cur[2], acc);
         if (kk + 1 < KK) {
@@ -188,7 +196,7 @@ template <bool CI4>
 __device__ __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc, int lane,
                                          int overwrite) {
     const int ninput = it.ninput;
-    uint8_t *obase = (uint8_t *)it.out;
+    uint8_t *obase = (uint8_t *)it.out + (int64_t)j.ochan * it.out_chan_bytes;
     const int g = lane >> 5;
     const int jj = j.cblk * kBlk + 32 * j.ch + (lane & 31);
     const int jmax_tile = j.cblk * kBlk + 32 * j.ch + 31;
@@ -234,6 +242,7 @@ __device__ inline void zero_acc(Acc &acc) {
 template <bool CI4>
 struct IntConsumer {
     typedef bfx::Acc Acc;
+    typedef StageRaw<CI4> Raw;
     struct Bases {
         int fb[3];
     };
@@ -243,8 +252,11 @@ struct IntConsumer {
         b.fb[1] = frag_base<CI4>(job.rrow + 32, lane);
         b.fb[2] = frag_base<CI4>(job.crow, lane);
     }
-    __device__ static __forceinline__ void stage(const uint8_t *st, const Bases &b, Acc &acc) {
-        mfma_stage<CI4>(st, b.fb, acc);
+    __device__ static __forceinline__ void read(const uint8_t *st, const Bases &b, Raw &raw) {
+        read_stage<CI4>(st, b.fb, raw);
+    }
+    __device__ static __forceinline__ void compute(const Raw &raw, Acc &acc) {
+        mfma_stage<CI4>(raw, acc);
     }
     __device__ static __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc,
                                                     int lane, int overwrite) {
@@ -275,12 +287,17 @@ struct BatchArray {
         const int2 e = work[B];
         if (e.x < 0) return false;
         const BatchUnit &u = units[e.x & ((1 << kBatchSubBits) - 1)];
-        it.item = e.x >> kBatchSubBits;
+        const int field = (e.x & ~kBatchPacked) >> kBatchSubBits;
+        const bool packed = e.x & kBatchPacked;
+        it.item = packed ? 0 : field;
+        it.npack = packed ? field : 0;
         it.ninput = u.ninput;
         it.nb = u.nb;
         it.t_stride = u.t_stride;
-        it.base = arena + ntime * u.in_row_off + t0 * u.t_stride + (int64_t)e.y * u.ninput * bps;
-        it.out = out + u.out_off + (int64_t)e.y * ((int64_t)u.ninput * (u.ninput + 1) / 2 * 8);
+        it.chan_bytes = (int64_t)u.ninput * bps;
+        it.out_chan_bytes = (int64_t)u.ninput * (u.ninput + 1) / 2 * 8;
+        it.base = arena + ntime * u.in_row_off + t0 * u.t_stride + (int64_t)e.y * it.chan_bytes;
+        it.out = out + u.out_off + (int64_t)e.y * it.out_chan_bytes;
         return true;
     }
 };
@@ -318,7 +335,10 @@ void init_once() {
 
 }  // namespace
 
-int xengine_tri_items(int32_t ninput) { return tri_items((ninput + kBlk - 1) / kBlk); }
+int64_t xengine_items(int32_t ninput, int32_t nchan) {
+    const int nb = (ninput + kBlk - 1) / kBlk;
+    return nb == 1 ? ((int64_t)nchan + 3) / 4 : (int64_t)nchan * tri_items(nb);
+}
 
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               int32_t *out, bool overwrite, hipStream_t s) {
@@ -334,7 +354,9 @@ hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t ncha
     w.ninput = ninput;
     w.nb = (ninput + kBlk - 1) / kBlk;
     w.nitems = tri_items(w.nb);
-    const int64_t total_flat = ((int64_t)nchan + 7) / 8 * 8 * w.nitems;
+    w.npk = w.nb == 1 ? 4 : 1;
+    w.ngroups = (nchan + w.npk - 1) / w.npk;
+    const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
     if (ci4)
         hipLaunchKernelGGL(xengine_int_kernel<true>, dim3((unsigned)grid), dim3(kThreads),
