@@ -388,9 +388,12 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // do the MFMAs of stage s run -- so the LDS reads of one stage overlap the
 // matrix work of the previous one.  At an item's last stage the next item's
 // job is decoded first, so its first stage is read under the same overlap.
-// The vector-memory counter is in order for loads, but the epilogue's stores
-// share it and may complete out of order with them, so the first wait after
-// an epilogue (and the tail of the sequence) waits for everything.
+// The vector-memory counter also counts the epilogue's stores, which may
+// complete out of order with the loads; the DMA loads themselves complete in
+// order.  A wait for "at most N outstanding", N = the DMA loads issued after
+// the awaited stage, is therefore exact for the loads whatever the stores do:
+// while the awaited DMA is outstanding so is every later load, so at least
+// N + 1 operations are.  Pending stores can only lengthen the wait.
 template <class F, class C, class W>
 __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int overwrite) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -428,14 +431,18 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
 
     typename C::Acc acc;
     C::zero(acc);
-    typename C::Raw ra, rb;
+    // Both raw-fragment sets are defined on every path (zeroed here, then
+    // read unconditionally -- an inactive wave's bases still point inside the
+    // stage): left undefined on some path, the optimiser may drop the
+    // next->current copy at an item boundary.
+    typename C::Raw ra = {}, rb = {};
 
     for (int k = 0; k < kRing - 1 && P.valid; ++k)
         prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     wait_stage(P.issued - 1);
     block_barrier();
     if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-    if (job.active) C::read(lds, fb, ra);
+    C::read(lds, fb, ra);
     // Returned before the loop: the compiler's wait tracking merges the
     // entry and back-edge states at the loop header, and reads still pending
     // from the entry would make it wait for the next stage's reads as well
@@ -444,7 +451,6 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
 
     int s = 0;   // stage whose MFMA work this iteration does
     int cs = 0;  // its index within the current item
-    bool after_epilogue = false;
     while (true) {
         const bool last = cs + 1 == nst;
         WaveJob njob = job;
@@ -465,29 +471,27 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
         if (more) {
             // every read of stage s has returned: its slot may be refilled
             wait_lds();
-            if (after_epilogue) wait_vm<0>();
-            else wait_stage(P.issued - (s + 1) - 1);
+            wait_stage(P.issued - (s + 1) - 1);
             block_barrier();
             if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-            if (njob.active) C::read(lds + ((s + 1) % kRing) * kStageBytes, nfb, rb);
+            C::read(lds + ((s + 1) % kRing) * kStageBytes, nfb, rb);
         }
         __builtin_amdgcn_sched_barrier(0);  // the reads above go out before the MFMAs below
-        after_epilogue = false;
         if (job.active) C::compute(ra, acc);
         if (last) {
             if (job.active) C::epilogue(job, cit, acc, lane, overwrite);
             C::zero(acc);
-            if (!more) break;
             job = njob;
             fb = nfb;
             cit = nit;
-            cs = 0;
-            after_epilogue = true;
-        } else {
-            ++cs;
         }
+        // The next stage's fragments become current on every path, and the
+        // loop's only exit is the test below: with an exit between the
+        // epilogue and this copy, the copy was lost on the item-boundary path.
         ra = rb;
+        cs = last ? 0 : cs + 1;
         ++s;
+        if (!more) break;
     }
     wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
 }

@@ -171,3 +171,20 @@ def test_streaming_704_inputs_full_size():
     # exact identity on every channel
     re, im = oracle.unpack_ci4(raw)
     assert freivalds_check(got, re, im, seed=3)
+
+
+@pytest.mark.parametrize("dtype,T", [("ci8", 96), ("ci8", 256), ("ci8", 320), ("ci4", 512),
+                                     ("ci4", 640)])
+def test_items_span_several_rounds(dtype, T):
+    """512 channels of 96 inputs = 512 work items on a grid of one workgroup
+    per CU, so every workgroup runs at least two items back to back, with an
+    item length (stages of the LDS ring) below, equal to and above the ring
+    depth: the hand-over of the next item's first stage must be exact."""
+    F, N = 512, 96
+    banner(f"xengine {dtype} multi-round T={T} F={F} N={N}")
+    sigma, clip = (8.0, 127) if dtype == "ci8" else (2.5, 7)
+    raw = synth.voltages(60 + T, T, F, N, dtype, sigma, clip)
+    got = packed_vis(_run(raw, dtype, T, F, N), F, N)
+    want = oracle.xengine_int(raw, dtype, T, F, N)
+    bad = np.nonzero(np.any(got != want, axis=(1, 2)))[0]
+    assert bad.size == 0, f"{bad.size} channels differ, first {bad[:8].tolist()}"

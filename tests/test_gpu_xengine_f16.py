@@ -173,3 +173,14 @@ def test_fp16_full_size_sampled_channels(cf16_full):
     # E[V_ii] = T * 2 sigma^2 (sigma = 1), sd = sqrt(T * 2 * 2) per entry
     z = (auto[..., 0] - 2.0 * T) / np.sqrt(4.0 * T)
     assert abs(z.mean()) < 0.05 and 0.8 < z.std() < 1.2
+
+
+@pytest.mark.parametrize("T", [48, 128, 160])
+def test_fp16_items_span_several_rounds(T):
+    """512 work items (512 channels of 96 inputs) on one workgroup per CU:
+    consecutive items per workgroup, item lengths below, equal to and above
+    the LDS ring depth."""
+    F, N = 512, 96
+    banner(f"xengine cf16 multi-round T={T} F={F} N={N}")
+    x = synth.cf16_voltages(80 + T, T, F, N)
+    _check(_host(_run(x, T, F, N), F, N), _oracle(x), N, T, f"cf16 multi-round T={T}")
