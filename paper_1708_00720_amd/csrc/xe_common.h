@@ -38,17 +38,17 @@ typedef __attribute__((address_space(3))) v4s lds_v4s;
 
 constexpr int kBlk = 64;          // inputs per block / LDS slot
 constexpr int kSlots = 4;         // input blocks held per work item
-constexpr int kWaves = 8;         // two block-pair halves per SIMD
-constexpr int kDmaWaves = kWaves; // every wave issues part of each stage's DMA
-constexpr int kThreads = 64 * kWaves;
 constexpr int kStageBytes = 16384;
 constexpr int kRing = 8;          // LDS stages in flight (128 KiB)
 constexpr int kRingBytes = kRing * kStageBytes;
 // The ring plus 1 KiB that receives the dummy DMA of a chunk fetched by the
-// synchronous path (keeps every stage at exactly kDmaPerWave DMA operations
+// synchronous path (keeps every stage at exactly its DMA operation count
 // per wave, which the vmcnt waits count on).
 constexpr int kLdsBytes = kRingBytes + 1024;
-constexpr int kDmaPerWave = kStageBytes / 1024 / kDmaWaves;  // 16-byte-per-lane DMA instructions
+// Every wave of a workgroup issues an equal share of each stage's DMA
+// (16-byte-per-lane instructions, 1 KiB each).
+template <int NW>
+constexpr int dma_per_wave() { return kStageBytes / 1024 / NW; }
 
 // Layout of one LDS stage: kT time rows of 256 inputs of BPS bytes each
 // (1: ci4, 2: ci8, 4: cf16).
@@ -159,21 +159,6 @@ __device__ inline void wait_vm() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
 }
 
-// Wait until every DMA issued for stages up to the awaited one has landed,
-// given `ahead` stages issued after it (each kDmaPerWave instructions).
-__device__ __forceinline__ void wait_stage(int ahead) {
-    static_assert(kRing - 2 <= 6, "extend the cases below");
-    switch (ahead) {
-        case 6: wait_vm<6 * kDmaPerWave>(); break;
-        case 5: wait_vm<5 * kDmaPerWave>(); break;
-        case 4: wait_vm<4 * kDmaPerWave>(); break;
-        case 3: wait_vm<3 * kDmaPerWave>(); break;
-        case 2: wait_vm<2 * kDmaPerWave>(); break;
-        case 1: wait_vm<1 * kDmaPerWave>(); break;
-        default: wait_vm<0>(); break;
-    }
-}
-
 __device__ inline void block_barrier() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
@@ -186,39 +171,59 @@ __device__ const uint4 kZeroChunk = {0u, 0u, 0u, 0u};
 constexpr int kSchedValu = 0x2;
 constexpr int kSchedMfma = 0x8;
 
-// Per-wave view of the current compute item: wave w works on block pair
-// w % 4 of the item, column half w / 4 (the two waves of a pair share a SIMD).
+// Per-wave view of the current compute item: one block pair of the item
+// (row block rblk, column block cblk), or one 32-column half of it.
 struct WaveJob {
     int rblk, cblk, ch;
     int ochan;       // channel of the pair, relative to the item's first
-    int rrow, crow;  // LDS input offsets of the row block and of this wave's column half
-    bool active, diag, full;
-    unsigned live;   // bit r: sub-block (row half r, this column half) is needed
+    int rrow, crow;  // LDS input offsets of the row block and of this wave's columns
+    bool active, diag;
+    unsigned live;   // bit 2*r + c: 32x32 sub-block (row half r, column half c) is needed
 };
 
-__device__ inline WaveJob make_job(const Task &tk, int wave, int ninput) {
-    WaveJob j;
-    const int pw = wave & 3;
-    j.ch = wave >> 2;
-    const int rs = pick4(tk.rs, pw);
-    const int cs = pick4(tk.cs, pw);
+__device__ inline void job_common(const Task &tk, int pair, int ch, WaveJob &j) {
+    const int rs = pick4(tk.rs, pair);
+    const int cs = pick4(tk.cs, pair);
+    j.ch = ch;
     j.active = rs >= 0;
     j.rblk = j.active ? pick4(tk.blk, rs) : 0;
     j.cblk = j.active ? pick4(tk.blk, cs) : 0;
     j.ochan = j.active ? pick4(tk.chan, rs) : 0;
     j.rrow = (rs < 0 ? 0 : rs) * kBlk;
-    j.crow = (cs < 0 ? 0 : cs) * kBlk + 32 * j.ch;
+    j.crow = (cs < 0 ? 0 : cs) * kBlk + 32 * ch;
     j.diag = j.active && rs == cs;
+}
+
+// Sub-block (r, c) of a pair holds a needed output: inside the array and not
+// entirely above the diagonal of a diagonal pair.
+__device__ inline bool sub_live(const WaveJob &j, int r, int c, int ninput) {
+    return j.rblk * kBlk + 32 * r < ninput && j.cblk * kBlk + 32 * c < ninput &&
+           !(j.diag && r < c);
+}
+
+// Eight waves: wave w works on block pair w % 4, column half w / 4 (the two
+// waves of a pair share a SIMD).  live bits 2*r + ch.
+__device__ inline WaveJob make_job_half(const Task &tk, int wave, int ninput) {
+    WaveJob j;
+    job_common(tk, wave & 3, wave >> 2, j);
     j.live = 0;
-    if (j.active) {
-        for (int r = 0; r < 2; ++r) {
-            const bool ok = j.rblk * kBlk + 32 * r < ninput && j.cblk * kBlk + 32 * j.ch < ninput &&
-                            !(j.diag && r == 0 && j.ch == 1);
-            if (ok) j.live |= 1u << r;
-        }
-    }
+    if (j.active)
+        for (int r = 0; r < 2; ++r)
+            if (sub_live(j, r, j.ch, ninput)) j.live |= 1u << (2 * r + j.ch);
     j.active = j.live != 0;
-    j.full = j.live == 3u;
+    return j;
+}
+
+// Four waves: wave w works on the whole block pair w.
+__device__ inline WaveJob make_job_pair(const Task &tk, int wave, int ninput) {
+    WaveJob j;
+    job_common(tk, wave, 0, j);
+    j.live = 0;
+    if (j.active)
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c)
+                if (sub_live(j, r, c, ninput)) j.live |= 1u << (2 * r + c);
+    j.active = j.live != 0;
     return j;
 }
 
@@ -274,42 +279,52 @@ struct SingleArray {
 // ahead.  Per item it holds, for each of this lane's DMA instructions, the
 // byte offset of its chunk from the item's time-row base and (bit ii of
 // okmask) whether the chunk lies inside the array.
+template <int DPW>
 struct Producer {
-    int B, ps, issued;
+    int B, ps;
+    unsigned issued;       // stages issued so far (real or dummy)
     bool valid, straddle;
     int okmask;
     Item it;
-    int64_t d_off[kDmaPerWave];
-    int inp[kDmaPerWave];  // first input of each chunk within its channel
+    const uint8_t *row;    // time row of the next stage of the current item
+    const uint8_t *zero;   // a 16-byte zero chunk
+    int64_t d_off[DPW];
+    int inp[DPW];          // first input of each chunk within its channel
 };
 
 // Geometry of DMA instruction ii of DMA wave dw: the stage row this lane
 // fetches, and the LDS slot and first input (within the slot) of its chunk.
-template <class F>
+template <class F, int DPW>
 __device__ __forceinline__ void dma_geom(int dw, int ii, int lane, int &row, int &slot, int &inp) {
-    row = (dw * kDmaPerWave + ii) * F::kRowsPerDma + lane / F::kChunks;
+    row = (dw * DPW + ii) * F::kRowsPerDma + lane / F::kChunks;
     const int c = (lane % F::kChunks) ^ F::swz(row);
     slot = c / F::kChunksPerSlot;
     inp = (c % F::kChunksPerSlot) * F::kInputsPerChunk;
 }
 
-template <class F>
-__device__ __forceinline__ void prod_item(Producer &P, int dw, int lane) {
+template <class F, int DPW>
+__device__ __forceinline__ void prod_item(Producer<DPW> &P, int dw, int lane) {
     Task tk;
     decode_task(P.it, tk);
     P.okmask = 0;
 #pragma unroll
-    for (int ii = 0; ii < kDmaPerWave; ++ii) {
+    for (int ii = 0; ii < DPW; ++ii) {
         int row, slot, inp0;
-        dma_geom<F>(dw, ii, lane, row, slot, inp0);
+        dma_geom<F, DPW>(dw, ii, lane, row, slot, inp0);
         const int blk = pick4(tk.blk, slot);
         const int inp = blk * kBlk + inp0;
         const bool ok = blk >= 0 && inp < P.it.ninput;
         P.okmask |= ok ? (1 << ii) : 0;
-        P.d_off[ii] = (int64_t)row * P.it.t_stride + (int64_t)pick4(tk.chan, slot) * P.it.chan_bytes +
-                      (int64_t)inp * F::kBps;
+        // A chunk outside the array (an unused slot, or inputs past ninput)
+        // fetches input 0 of the same row instead: such LDS inputs only feed
+        // outputs that are never stored (every output depends on its own two
+        // inputs alone), so no zero fill is needed -- except past the last
+        // time row, which the slow path zero-fills.
+        P.d_off[ii] = (int64_t)row * P.it.t_stride +
+                      (ok ? (int64_t)pick4(tk.chan, slot) * P.it.chan_bytes + (int64_t)inp * F::kBps : 0);
         P.inp[ii] = inp;
     }
+    P.row = P.it.base;
     // A chunk can run past ninput only in the block holding the last input,
     // and only when ninput is not a multiple of the inputs per chunk.
     const int last = (P.it.ninput - 1) / kBlk;
@@ -317,58 +332,67 @@ __device__ __forceinline__ void prod_item(Producer &P, int dw, int lane) {
                  (tk.blk[0] == last || tk.blk[1] == last || tk.blk[2] == last || tk.blk[3] == last);
 }
 
-template <class F, class W>
-__device__ __forceinline__ void prod_advance(Producer &P, const W &w, int total_flat, int grid,
+template <class F, int DPW, class W>
+__device__ __forceinline__ void prod_advance(Producer<DPW> &P, const W &w, int total_flat, int grid,
                                              int dw, int lane) {
     P.valid = false;
     while (P.B < total_flat && !(P.valid = w.get(P.B, P.it))) P.B += grid;
-    if (P.valid) prod_item<F>(P, dw, lane);
+    if (P.valid) prod_item<F, DPW>(P, dw, lane);
 }
 
-template <class F, class W>
-__device__ __forceinline__ void prod_issue(Producer &P, const W &w, int nt, int nst, int total_flat,
-                                           int grid, uint8_t *lds, uint32_t lds_base, int dw,
-                                           int lane) {
-    const uint8_t *zero = (const uint8_t *)&kZeroChunk;
-    const int slot = P.issued % kRing;
-    const uint32_t sbase = lds_base + slot * kStageBytes + dw * kDmaPerWave * 1024;
+// Issue the next stage's DMA into ring slot issued % kRing.  Past the end of
+// the work sequence the producer keeps issuing a dummy stage (zero chunks into
+// the slot just consumed), so that exactly kRing - 2 stages are always in
+// flight after the awaited one and every wait is the same constant.
+template <class F, int DPW, class W>
+__device__ __forceinline__ void prod_issue(Producer<DPW> &P, const W &w, int nt, int nst,
+                                           int total_flat, int grid, uint8_t *lds, uint32_t lds_base,
+                                           int dw, int lane) {
+    const unsigned slot = P.issued & (kRing - 1);
+    const uint32_t sbase = lds_base + slot * kStageBytes + dw * DPW * 1024;
+    ++P.issued;
+    if (!P.valid) {
+#pragma unroll
+        for (int ii = 0; ii < DPW; ++ii) dma16(P.zero, sbase + ii * 1024);
+        return;
+    }
+    const uint8_t *rowbase = P.row;
     const int t0 = P.ps * F::kT;
-    const uint8_t *rowbase = P.it.base + (int64_t)t0 * P.it.t_stride;
     if (!P.straddle && t0 + F::kT <= nt) {
         // fast path: every row of the stage exists and no chunk straddles
 #pragma unroll
-        for (int ii = 0; ii < kDmaPerWave; ++ii)
-            dma16(((P.okmask >> ii) & 1) ? rowbase + P.d_off[ii] : zero, sbase + ii * 1024);
+        for (int ii = 0; ii < DPW; ++ii) dma16(rowbase + P.d_off[ii], sbase + ii * 1024);
     } else {
 #pragma unroll
-        for (int ii = 0; ii < kDmaPerWave; ++ii) {
+        for (int ii = 0; ii < DPW; ++ii) {
             int row, sl, inp0;
-            dma_geom<F>(dw, ii, lane, row, sl, inp0);
+            dma_geom<F, DPW>(dw, ii, lane, row, sl, inp0);
             const int t = t0 + row;
             const int inp = P.inp[ii];
             const bool ok = ((P.okmask >> ii) & 1) && t < nt;
             const bool straddle = ok && inp + F::kInputsPerChunk > P.it.ninput;
-            if (!straddle) dma16(ok ? rowbase + P.d_off[ii] : zero, sbase + ii * 1024);
+            if (!straddle) dma16(ok ? rowbase + P.d_off[ii] : P.zero, sbase + ii * 1024);
             if (straddle) {
-                // chunk runs past the last input: fetch whole 4-byte words
-                // (ninput % 4 == 0) and zero-fill the rest; a DMA of the zero
-                // chunk into the spare kilobyte keeps the per-stage count.
-                dma16(zero, lds_base + kRingBytes);
+                // chunk runs past the last input (possibly the end of the
+                // buffer): fetch whole 4-byte words (ninput % 4 == 0) and
+                // zero-fill the rest; a DMA of the zero chunk into the spare
+                // kilobyte keeps the per-stage count.
+                dma16(P.zero, lds_base + kRingBytes);
                 const uint8_t *p = rowbase + P.d_off[ii];
                 const int nwords = ((P.it.ninput - inp) * F::kBps) / 4;
                 uint32_t wd[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) wd[k] = k < nwords ? ((const uint32_t *)p)[k] : 0u;
-                uint8_t *l = lds + slot * kStageBytes + (dw * kDmaPerWave + ii) * 1024 + lane * 16;
+                uint8_t *l = lds + slot * kStageBytes + (dw * DPW + ii) * 1024 + lane * 16;
                 *(uint4 *)l = uint4{wd[0], wd[1], wd[2], wd[3]};
             }
         }
     }
-    ++P.issued;
+    P.row += (int64_t)F::kT * P.it.t_stride;
     if (++P.ps == nst) {
         P.ps = 0;
         P.B += grid;
-        prod_advance<F>(P, w, total_flat, grid, dw, lane);
+        prod_advance<F, DPW>(P, w, total_flat, grid, dw, lane);
     }
 }
 
@@ -378,6 +402,7 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // The persistent loop shared by every X-engine kernel, software-pipelined
 // across stages.  F is the LDS row format, C the consumer policy:
+//   C::kWaves (waves per workgroup), C::job(task, wave, ninput);
 //   C::Acc, C::Raw, C::Bases;  C::zero(acc);  C::bind(job, lane, bases);
 //   C::read(stage_ptr, bases, raw)   -- issue the stage's transposing LDS reads;
 //   C::compute(raw, acc)             -- the stage's MFMA work from registers;
@@ -402,7 +427,8 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
     const int lane = tid & 63;
-    const int dw = wave;  // every wave issues kDmaPerWave of each stage's DMA
+    const int dw = wave;  // every wave issues DPW of each stage's DMA
+    constexpr int DPW = dma_per_wave<C::kWaves>();
     const int grid = gridDim.x;
     const int nst = (nt + F::kT - 1) / F::kT;
 
@@ -414,18 +440,19 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     if (!cvalid) return;  // no work for this workgroup
 
     // ---- producer cursor (every wave issues its share of each stage)
-    Producer P;
+    Producer<DPW> P;
     P.B = blockIdx.x;
     P.ps = 0;
     P.issued = 0;
-    prod_advance<F>(P, w, total_flat, grid, dw, lane);
+    P.zero = (const uint8_t *)&kZeroChunk;
+    prod_advance<F, DPW>(P, w, total_flat, grid, dw, lane);
 
     WaveJob job;
     typename C::Bases fb;
     {
         Task tk;
         decode_task(cit, tk);
-        job = make_job(tk, wave, cit.ninput);
+        job = C::job(tk, wave, cit.ninput);
         C::bind(job, lane, fb);
     }
 
@@ -437,11 +464,12 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     // next->current copy at an item boundary.
     typename C::Raw ra = {}, rb = {};
 
-    for (int k = 0; k < kRing - 1 && P.valid; ++k)
-        prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-    wait_stage(P.issued - 1);
+    constexpr int kAhead = (kRing - 2) * DPW;  // DMA operations after the awaited stage
+    for (int k = 0; k < kRing - 1; ++k)
+        prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    wait_vm<kAhead>();
     block_barrier();
-    if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     C::read(lds, fb, ra);
     // Returned before the loop: the compiler's wait tracking merges the
     // entry and back-edge states at the loop header, and reads still pending
@@ -449,8 +477,8 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     // before the current stage's MFMAs.
     wait_lds();
 
-    int s = 0;   // stage whose MFMA work this iteration does
-    int cs = 0;  // its index within the current item
+    unsigned s = 0;  // stage whose MFMA work this iteration does
+    int cs = 0;      // its index within the current item
     while (true) {
         const bool last = cs + 1 == nst;
         WaveJob njob = job;
@@ -464,17 +492,17 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
             if (more) {
                 Task tk;
                 decode_task(nit, tk);
-                njob = make_job(tk, wave, nit.ninput);
+                njob = C::job(tk, wave, nit.ninput);
                 C::bind(njob, lane, nfb);
             }
         }
         if (more) {
             // every read of stage s has returned: its slot may be refilled
             wait_lds();
-            wait_stage(P.issued - (s + 1) - 1);
+            wait_vm<kAhead>();
             block_barrier();
-            if (P.valid) prod_issue<F>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-            C::read(lds + ((s + 1) % kRing) * kStageBytes, nfb, rb);
+            prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+            C::read(lds + ((s + 1) & (kRing - 1)) * kStageBytes, nfb, rb);
         }
         __builtin_amdgcn_sched_barrier(0);  // the reads above go out before the MFMAs below
         if (job.active) C::compute(ra, acc);

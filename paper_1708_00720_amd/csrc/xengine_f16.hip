@@ -75,6 +75,8 @@ __device__ __forceinline__ v8h read_frag16(const uint8_t *p) {
 }
 
 struct F16Consumer {
+    static constexpr int kWaves = 8;
+    static constexpr int kThreads = 64 * kWaves;
     typedef F16Acc Acc;
     struct Raw {
         v8h a[4], b[2];  // row and column fragments of one stage
@@ -82,6 +84,9 @@ struct F16Consumer {
     struct Bases {
         int fb[6];  // 4 row fragments, 2 column fragments
     };
+    __device__ static __forceinline__ WaveJob job(const Task &tk, int wave, int ninput) {
+        return make_job_half(tk, wave, ninput);
+    }
     __device__ static __forceinline__ void zero(Acc &acc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -167,7 +172,7 @@ struct F16Consumer {
     }
 };
 
-__global__ __launch_bounds__(kThreads, 1) void xengine_f16_kernel(SingleArray w, int nt,
+__global__ __launch_bounds__(F16Consumer::kThreads, 1) void xengine_f16_kernel(SingleArray w, int nt,
                                                                   int total_flat, int overwrite) {
     xe_loop<F16Fmt, F16Consumer>(w, nt, total_flat, overwrite);
 }
@@ -208,7 +213,7 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     w.ngroups = (nchan + w.npk - 1) / w.npk;
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
-    hipLaunchKernelGGL(xengine_f16_kernel, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, s, w,
+    hipLaunchKernelGGL(xengine_f16_kernel, dim3((unsigned)grid), dim3(F16Consumer::kThreads), kLdsBytes, s, w,
                        (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();
 }

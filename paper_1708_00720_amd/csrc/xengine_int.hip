@@ -9,8 +9,8 @@
 // Split into real products (a = Re x, b = Im x, sums over t):
 //   Re V_ij = sum a_i a_j + b_i b_j
 //   Im V_ij = P_ij - Q_ij,  P_ij = sum b_i a_j,  Q_ij = sum a_i b_j
-// Three accumulators per output tile (Re, P, Q) and no negated operand: the
-// full int8 range (including -128) is exact.
+// Accumulators per output tile (Re as two sums, P, Q) and no negated operand:
+// the full int8 range (including -128) is exact.
 //
 // Work decomposition, LDS ring and persistent loop: xe_common.h.  Per stage a
 // wave issues all of its transposing reads first: ds_read_b64_tr_b8 (ci4: 8
@@ -39,9 +39,12 @@ struct Fmt : RowFmt<CI4 ? 1 : 2> {
     static constexpr int kKK = RowFmt<CI4 ? 1 : 2>::kT / 32;
 };
 
-// A wave's 64x32 tile: two 32x32 sub-blocks (row halves r = 0, 1).
+// A wave's 64x32 tile: two 32x32 sub-blocks (row halves r = 0, 1), each with
+// four int32 accumulators: RR = sum a a, II = sum b b (Re V = RR + II),
+// P = sum b a, Q = sum a b (Im V = P - Q).  Separate RR and II keep the eight
+// MFMAs of a 32-sample step independent of each other.
 struct Acc {
-    v16i re[2], p[2], q[2];
+    v16i rr[2], ii[2], p[2], q[2];
 };
 
 // Packed-voltage fragment of a 32-input sub-block for one 32-sample step:
@@ -127,15 +130,14 @@ __device__ __forceinline__ Frag split_frag(const RawFrag<CI4> &r) {
 }
 
 __device__ __forceinline__ void mfma8(const Frag &a0, const Frag &a1, const Frag &b, Acc &acc) {
-    // the two MFMAs adding into acc.re are separated by the others
-    acc.re[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.re, acc.re[0], 0, 0, 0);
-    acc.re[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.re, acc.re[1], 0, 0, 0);
+    acc.rr[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.re, acc.rr[0], 0, 0, 0);
+    acc.rr[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.re, acc.rr[1], 0, 0, 0);
     acc.p[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.re, acc.p[0], 0, 0, 0);
     acc.p[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.re, acc.p[1], 0, 0, 0);
     acc.q[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.im, acc.q[0], 0, 0, 0);
     acc.q[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.im, acc.q[1], 0, 0, 0);
-    acc.re[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.im, acc.re[0], 0, 0, 0);
-    acc.re[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.im, acc.re[1], 0, 0, 0);
+    acc.ii[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.im, acc.ii[0], 0, 0, 0);
+    acc.ii[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.im, acc.ii[1], 0, 0, 0);
 }
 
 // Raw transposing reads of one stage of a wave's 64x32 tile: per 32-sample
@@ -202,7 +204,7 @@ __device__ __forceinline__ void epilogue(const WaveJob &j, const Item &it, const
     const int jmax_tile = j.cblk * kBlk + 32 * j.ch + 31;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        if (!((j.live >> r) & 1u)) continue;
+        if (!((j.live >> (2 * r + j.ch)) & 1u)) continue;
         const int irow0 = j.rblk * kBlk + 32 * r;  // first row of the sub-block
         const int i0 = irow0 + 4 * g;
         const uint32_t base = (uint32_t)((i0 * (i0 + 1) / 2 + jj) * 8);
@@ -213,7 +215,7 @@ __device__ __forceinline__ void epilogue(const WaveJob &j, const Item &it, const
         for (int v = 0; v < 16; ++v) {
             const int d = 8 * (v >> 2) + (v & 3);
             const uint32_t off = base + (uint32_t)d * step + (uint32_t)(d * (d + 1) / 2 * 8);
-            int vr = acc.re[r][v];
+            int vr = acc.rr[r][v] + acc.ii[r][v];
             int vi = acc.p[r][v] - acc.q[r][v];
             if (CI4) { vr >>= 8; vi >>= 8; }
             const int i = i0 + d;
@@ -233,19 +235,27 @@ __device__ __forceinline__ void epilogue(const WaveJob &j, const Item &it, const
 __device__ inline void zero_acc(Acc &acc) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        acc.re[r] = v16i{0};
+        acc.rr[r] = v16i{0};
+        acc.ii[r] = v16i{0};
         acc.p[r] = v16i{0};
         acc.q[r] = v16i{0};
     }
 }
 
+// Eight waves, two per SIMD: wave w works on 32 columns of block pair w % 4
+// (a 64x32 tile with the three accumulators of two 32x32 sub-blocks).
 template <bool CI4>
 struct IntConsumer {
+    static constexpr int kWaves = 8;
+    static constexpr int kThreads = 64 * kWaves;
     typedef bfx::Acc Acc;
     typedef StageRaw<CI4> Raw;
     struct Bases {
         int fb[3];
     };
+    __device__ static __forceinline__ WaveJob job(const Task &tk, int wave, int ninput) {
+        return make_job_half(tk, wave, ninput);
+    }
     __device__ static __forceinline__ void zero(Acc &acc) { zero_acc(acc); }
     __device__ static __forceinline__ void bind(const WaveJob &job, int lane, Bases &b) {
         b.fb[0] = frag_base<CI4>(job.rrow, lane);
@@ -265,7 +275,7 @@ struct IntConsumer {
 };
 
 template <bool CI4>
-__global__ __launch_bounds__(kThreads, 1) void xengine_int_kernel(SingleArray w, int nt,
+__global__ __launch_bounds__(IntConsumer<CI4>::kThreads, 1) void xengine_int_kernel(SingleArray w, int nt,
                                                                   int total_flat, int overwrite) {
     xe_loop<Fmt<CI4>, IntConsumer<CI4>>(w, nt, total_flat, overwrite);
 }
@@ -303,7 +313,7 @@ struct BatchArray {
 };
 
 template <bool CI4>
-__global__ __launch_bounds__(kThreads, 1) void xengine_batched_kernel(BatchArray w, int nt,
+__global__ __launch_bounds__(IntConsumer<CI4>::kThreads, 1) void xengine_batched_kernel(BatchArray w, int nt,
                                                                       int total_flat,
                                                                       int overwrite) {
     xe_loop<Fmt<CI4>, IntConsumer<CI4>>(w, nt, total_flat, overwrite);
@@ -359,10 +369,10 @@ hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t ncha
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
     if (ci4)
-        hipLaunchKernelGGL(xengine_int_kernel<true>, dim3((unsigned)grid), dim3(kThreads),
+        hipLaunchKernelGGL(xengine_int_kernel<true>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
     else
-        hipLaunchKernelGGL(xengine_int_kernel<false>, dim3((unsigned)grid), dim3(kThreads),
+        hipLaunchKernelGGL(xengine_int_kernel<false>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();
 }
@@ -382,10 +392,10 @@ hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, in
     w.bps = ci4 ? 1 : 2;
     const int64_t grid = persistent_grid(g_num_cus, nwork);
     if (ci4)
-        hipLaunchKernelGGL(xengine_batched_kernel<true>, dim3((unsigned)grid), dim3(kThreads),
+        hipLaunchKernelGGL(xengine_batched_kernel<true>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
     else
-        hipLaunchKernelGGL(xengine_batched_kernel<false>, dim3((unsigned)grid), dim3(kThreads),
+        hipLaunchKernelGGL(xengine_batched_kernel<false>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
     return hipGetLastError();
 }
