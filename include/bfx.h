@@ -170,7 +170,7 @@ bfx_status bfx_xengine_dump(bfx_xengine *plan, const void *d_acc, void *d_out, d
  *   nfft     transform length, a power of two in [64, 8192];
  *   ninput   positive, even;
  *            (this build implements nfft = 4096 with ninput a multiple of
- *            16 and returns BFX_ENOTSUP for the other valid shapes);
+ *            8 and returns BFX_ENOTSUP for the other valid shapes);
  *   nspec    number of non-overlapping frames per input (rectangular window);
  *   d_scale  device float[nfft/2], per-channel requantization scale (ignored
  *            for BFX_CF32 output);

@@ -394,7 +394,7 @@ bfx_status bfx_fengine(const int8_t *d_in, int32_t ninput, int32_t nfft, int64_t
     if (nspec <= 0 || nspec > ((int64_t)1 << 28))
         return fail(BFX_EINVAL, "nspec=%lld out of range", (long long)nspec);
     if (!fengine_supported(ninput, nfft))
-        return fail(BFX_ENOTSUP, "this build transforms nfft=4096 with ninput a multiple of 16 "
+        return fail(BFX_ENOTSUP, "this build transforms nfft=4096 with ninput a multiple of 8 "
                                  "(got nfft=%d, ninput=%d)", nfft, ninput);
     hipError_t e = launch_fengine(d_in, ninput, nfft, nspec, d_scale, d_out, out == BFX_CI8,
                                   (hipStream_t)stream);
