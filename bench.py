@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "X-engine TeraCMAC/s + input GB/s at 704 inputs; int8 exact vs FP16/FP32 path"
 N_INPUT, N_CHAN, N_TIME, N_GULP, N_SLOT = 704, 192, 1000, 100, 4
 PEAK_INT8_TOPS = 5000.0  # MI355X dense int8 MFMA, 5.0 POP/s
-KERNEL_SRC = os.path.join(ROOT, "paper_1708_00720_amd", "csrc", "xengine_int.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1708_00720_amd", "csrc", f)
+               for f in ("xengine_int.hip", "xe_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xengine_int_ci4_704_traffic.json")
 
 
@@ -35,8 +36,12 @@ def cmac_per_gulp():
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources the integer X-engine kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(per_launch_cmac):
@@ -71,7 +76,10 @@ def cpu_baseline(raw_gulp, budget_s=15.0):
 
 
 PEAK_FP16_TFLOPS = 2500.0  # MI355X dense FP16 MFMA
-PEAK_FP32_TFLOPS = 157.3   # FP32 vector
+PEAK_FP32_TFLOPS = 157.3   # FP32 vector, counting packed (two-per-lane) FMA
+# FP32 vector without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz.  The kernels are built with packed FP32 disabled.
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -133,9 +141,10 @@ def row_fengine(reps):
     nbytes = S * NFFT * N + S * (NFFT // 2) * N * 2
     flops = int(2.5 * NFFT * 12) * S * N
     r = _row("fengine_kernel<ci8>", "256 inputs x 512 frames x 4096-point real FFT -> ci8",
-             avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
-             {"fft_flops_per_launch": flops,
-              "fp32_alu_frac": round(flops / (avg * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+             avg, med, flops, "flops", round(PEAK_FP32_UNPACKED_TFLOPS, 1), "TFLOP/s", "alu",
+             nbytes,
+             {"hbm_frac_algorithmic": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+              "fp32_frac_of_packed_peak": round(flops / (avg * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
               "msamples_per_s": round(S * NFFT * N / (avg * 1e-3) / 1e6, 1)})
     del x, out
     return r
