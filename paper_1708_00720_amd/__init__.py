@@ -22,6 +22,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is not built; run paper_1708_00720_amd/build.py (or __graft_entry__.build())")
 
+# torch ships its own HIP runtime: load it before libbfx.so so that the
+# library binds to that same runtime (a second copy loaded first leaves torch
+# without a device).
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # status codes and dtypes (include/bfx.h)

@@ -17,7 +17,7 @@
 // Data path.  A ring of kRing LDS stages of 16 KiB receives raw time rows of
 // the four blocks (256 inputs) straight from HBM with global_load_lds_dwordx4
 // (no staging registers), kRing-1 stages ahead of the MFMA work and across
-// work-item boundaries; every wave issues two of each stage's 16 DMA
+// work-item boundaries; one wave per SIMD issues four of each stage's 16 DMA
 // instructions and waits on its own vector-memory counter before the stage
 // barrier.  Each row's 16-byte chunks are XOR-swizzled by the row index so the
 // consumers' transposing LDS reads are free of bank conflicts.
@@ -45,7 +45,7 @@ constexpr int kRingBytes = kRing * kStageBytes;
 // synchronous path (keeps every stage at exactly its DMA operation count
 // per wave, which the vmcnt waits count on).
 constexpr int kLdsBytes = kRingBytes + 1024;
-// Every wave of a workgroup issues an equal share of each stage's DMA
+// Each of NW DMA waves issues an equal share of each stage's DMA
 // (16-byte-per-lane instructions, 1 KiB each).
 template <int NW>
 constexpr int dma_per_wave() { return kStageBytes / 1024 / NW; }
@@ -403,16 +403,26 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // The persistent loop shared by every X-engine kernel, software-pipelined
 // across stages.  F is the LDS row format, C the consumer policy:
 //   C::kWaves (waves per workgroup), C::job(task, wave, ninput);
-//   C::Acc, C::Raw, C::Bases;  C::zero(acc);  C::bind(job, lane, bases);
-//   C::read(stage_ptr, bases, raw)   -- issue the stage's transposing LDS reads;
-//   C::compute(raw, acc)             -- the stage's MFMA work from registers;
+//   C::Acc, C::Raw (a stage's transposing-read results), C::Pre (operands of
+//   a stage's first MFMA step, formed ahead), C::Bases;
+//   C::zero(acc);  C::bind(job, lane, bases);
+//   C::read(stage_ptr, bases, raw)  -- issue the stage's transposing LDS reads;
+//   C::prep(raw, pre)               -- form pre from raw;
+//   C::head(pre, raw, acc)          -- the stage's first MFMAs, from pre;
+//   C::tail(pre, raw, nraw, npre, acc) -- the rest of the stage's MFMAs, and
+//                                      npre from the next stage's nraw;
 //   C::epilogue(job, it, acc, lane, overwrite).
-// Iteration s: every wave waits for its own DMA of stage s+1, the barrier
-// publishes it, the ring slot of stage s (read completely by every wave before
-// the barrier) is refilled, the reads of stage s+1 are issued, and only then
-// do the MFMAs of stage s run -- so the LDS reads of one stage overlap the
-// matrix work of the previous one.  At an item's last stage the next item's
-// job is decoded first, so its first stage is read under the same overlap.
+// Iteration s: every DMA wave waits for its own DMA of stage s+1, the
+// barrier publishes it, and the MFMAs of stage s start at once from operands
+// already in registers.  Behind the first of them the ring slot of stage s
+// (read completely by every wave before the barrier) is refilled and the
+// reads of stage s+1 are issued; the remaining MFMAs of stage s then cover
+// those reads and the forming of stage s+1's first operands.  Only the first
+// kDmaWaves waves (one per SIMD) issue DMA: the other wave of each SIMD goes
+// straight on to its MFMAs while its partner does the producer's work.  At an item's last stage the
+// next item's job is decoded first, so its first stage is read under the same
+// overlap.  The loop body runs twice per trip with the two register sets
+// swapped, so no operand is copied.
 // The vector-memory counter also counts the epilogue's stores, which may
 // complete out of order with the loads; the DMA loads themselves complete in
 // order.  A wait for "at most N outstanding", N = the DMA loads issued after
@@ -427,8 +437,11 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
     const int lane = tid & 63;
-    const int dw = wave;  // every wave issues DPW of each stage's DMA
-    constexpr int DPW = dma_per_wave<C::kWaves>();
+    constexpr int kDmaWaves = 4;
+    static_assert(C::kWaves % kDmaWaves == 0, "DMA waves spread over the SIMDs");
+    const bool dma_wave = wave < kDmaWaves;
+    const int dw = wave;  // DMA waves issue DPW of each stage's DMA each
+    constexpr int DPW = dma_per_wave<kDmaWaves>();
     const int grid = gridDim.x;
     const int nst = (nt + F::kT - 1) / F::kT;
 
@@ -445,7 +458,7 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     P.ps = 0;
     P.issued = 0;
     P.zero = (const uint8_t *)&kZeroChunk;
-    prod_advance<F, DPW>(P, w, total_flat, grid, dw, lane);
+    if (dma_wave) prod_advance<F, DPW>(P, w, total_flat, grid, dw, lane);
 
     WaveJob job;
     typename C::Bases fb;
@@ -458,28 +471,30 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
 
     typename C::Acc acc;
     C::zero(acc);
-    // Both raw-fragment sets are defined on every path (zeroed here, then
-    // read unconditionally -- an inactive wave's bases still point inside the
-    // stage): left undefined on some path, the optimiser may drop the
-    // next->current copy at an item boundary.
+    // Both register sets are defined on every path (zeroed here, then read
+    // unconditionally while work remains -- an inactive wave's bases still
+    // point inside the stage).
     typename C::Raw ra = {}, rb = {};
+    typename C::Pre pa = {}, pb = {};
 
     constexpr int kAhead = (kRing - 2) * DPW;  // DMA operations after the awaited stage
-    for (int k = 0; k < kRing - 1; ++k)
-        prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    static_assert(kAhead + DPW < 64, "vmcnt range");
+    if (dma_wave)
+        for (int k = 0; k < kRing - 1; ++k)
+            prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     wait_vm<kAhead>();
     block_barrier();
-    prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    if (dma_wave) prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     C::read(lds, fb, ra);
-    // Returned before the loop: the compiler's wait tracking merges the
-    // entry and back-edge states at the loop header, and reads still pending
-    // from the entry would make it wait for the next stage's reads as well
-    // before the current stage's MFMAs.
     wait_lds();
+    C::prep(ra, pa);
 
-    unsigned s = 0;  // stage whose MFMA work this iteration does
+    unsigned s = 0;  // stage whose MFMA work the next step does
     int cs = 0;      // its index within the current item
-    while (true) {
+    // One stage: MFMAs of stage s from (cur, pcur); reads of stage s+1 into
+    // nxt and its first operands into pnxt.  Returns whether work remains.
+    auto step = [&](typename C::Raw &cur, typename C::Pre &pcur, typename C::Raw &nxt,
+                    typename C::Pre &pnxt) __attribute__((always_inline)) {
         const bool last = cs + 1 == nst;
         WaveJob njob = job;
         typename C::Bases nfb = fb;
@@ -501,11 +516,15 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
             wait_lds();
             wait_vm<kAhead>();
             block_barrier();
-            prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-            C::read(lds + ((s + 1) & (kRing - 1)) * kStageBytes, nfb, rb);
         }
-        __builtin_amdgcn_sched_barrier(0);  // the reads above go out before the MFMAs below
-        if (job.active) C::compute(ra, acc);
+        C::head(pcur, cur, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) {
+            if (dma_wave) prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+            C::read(lds + ((s + 1) & (kRing - 1)) * kStageBytes, nfb, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        C::tail(pcur, cur, nxt, pnxt, acc);
         if (last) {
             if (job.active) C::epilogue(job, cit, acc, lane, overwrite);
             C::zero(acc);
@@ -513,13 +532,11 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
             fb = nfb;
             cit = nit;
         }
-        // The next stage's fragments become current on every path, and the
-        // loop's only exit is the test below: with an exit between the
-        // epilogue and this copy, the copy was lost on the item-boundary path.
-        ra = rb;
         cs = last ? 0 : cs + 1;
         ++s;
-        if (!more) break;
+        return more;
+    };
+    while (step(ra, pa, rb, pb) && step(rb, pb, ra, pa)) {
     }
     wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
 }

@@ -105,12 +105,22 @@ struct F16Consumer {
 #pragma unroll
         for (int c = 0; c < 2; ++c) raw.b[c] = read_frag16(st + b.fb[4 + c]);
     }
-    __device__ static __forceinline__ void compute(const Raw &raw, Acc &acc) {
+    // The MFMA operands are the raw reads themselves: nothing is formed ahead.
+    struct Pre {};
+    __device__ static __forceinline__ void prep(const Raw &, Pre &) {}
+    // MFMA k of the stage: column fragment k / 4, row fragment k % 4.
+    __device__ static __forceinline__ void mfma_k(int k, const Raw &raw, Acc &acc) {
+        const int c = k >> 2, r = k & 3;
+        acc.c[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(raw.a[r], raw.b[c], acc.c[r][c], 0, 0, 0);
+    }
+    static constexpr int kHead = 2;
+    __device__ static __forceinline__ void head(const Pre &, const Raw &raw, Acc &acc) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int k = 0; k < kHead; ++k) mfma_k(k, raw, acc);
+    }
+    __device__ static __forceinline__ void tail(const Pre &, const Raw &raw, const Raw &, Pre &, Acc &acc) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc.c[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(raw.a[r], raw.b[c], acc.c[r][c], 0, 0, 0);
+        for (int k = kHead; k < 8; ++k) mfma_k(k, raw, acc);
     }
 
     // Swap with the neighbouring lane (DPP quad_perm [1,0,3,2]).
@@ -138,6 +148,17 @@ struct F16Consumer {
                 if (R0 + 15 < C0 || R0 >= ninput || C0 >= ninput) continue;  // dead sub-block
                 const bool interior = R0 >= C0 + 15 && R0 + 15 < ninput;
                 const v16f &v = acc.c[r][c];
+                const int jj = jl + 16 * c;
+                auto dst = [&](int s) {
+                    const int d = 16 * r + 4 * s;
+                    return (float2 *)(obase + base + (uint32_t)(16 * c * 8) + (uint32_t)d * step +
+                                      (uint32_t)(d * (d + 1) / 2 * 8));
+                };
+                auto ok = [&](int s) {
+                    const int i = il + 16 * r + 4 * s;
+                    return interior || (i < ninput && jj <= i);
+                };
+                float2 res[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const float send0 = odd ? v[4 * s] : v[4 * s + 2];
@@ -150,23 +171,25 @@ struct F16Consumer {
                     //            Im = C[im][re] (keep1) - C[re][im] (recv0);
                     // odd lane:  Re = C[re][re] (recv0) + C[im][im] (keep1),
                     //            Im = C[im][re] (recv1) - C[re][im] (keep0).
-                    float vr = (odd ? recv0 : keep0) + (odd ? keep1 : recv1);
-                    float vi = (odd ? recv1 : keep1) - (odd ? keep0 : recv0);
-                    const int d = 16 * r + 4 * s;
-                    const int i = il + d;
-                    const int jj = jl + 16 * c;
-                    if (interior || (i < ninput && jj <= i)) {
-                        const uint32_t off = base + (uint32_t)(16 * c * 8) + (uint32_t)d * step +
-                                             (uint32_t)(d * (d + 1) / 2 * 8);
-                        float2 *dst = (float2 *)(obase + off);
-                        if (!overwrite) {
-                            const float2 old = *dst;
-                            vr += old.x;
-                            vi += old.y;
-                        }
-                        *dst = float2{vr, vi};
-                    }
+                    res[s] = float2{(odd ? recv0 : keep0) + (odd ? keep1 : recv1),
+                                    (odd ? recv1 : keep1) - (odd ? keep0 : recv0)};
                 }
+                if (!overwrite) {
+                    // all old values first, then the sums, then the stores
+                    float2 old[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        old[s] = float2{0.0f, 0.0f};
+                        if (ok(s)) old[s] = *dst(s);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) res[s] = float2{res[s].x + old[s].x, res[s].y + old[s].y};
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    if (ok(s)) *dst(s) = res[s];
             }
         }
     }

@@ -9,7 +9,7 @@
 // Split into real products (a = Re x, b = Im x, sums over t):
 //   Re V_ij = sum a_i a_j + b_i b_j
 //   Im V_ij = P_ij - Q_ij,  P_ij = sum b_i a_j,  Q_ij = sum a_i b_j
-// Accumulators per output tile (Re as two sums, P, Q) and no negated operand:
+// Accumulators per output tile (Re, P, Q) and no negated operand:
 // the full int8 range (including -128) is exact.
 //
 // Work decomposition, LDS ring and persistent loop: xe_common.h.  Per stage a
@@ -40,11 +40,11 @@ struct Fmt : RowFmt<CI4 ? 1 : 2> {
 };
 
 // A wave's 64x32 tile: two 32x32 sub-blocks (row halves r = 0, 1), each with
-// four int32 accumulators: RR = sum a a, II = sum b b (Re V = RR + II),
-// P = sum b a, Q = sum a b (Im V = P - Q).  Separate RR and II keep the eight
-// MFMAs of a 32-sample step independent of each other.
+// three int32 accumulators: Re V = sum a a + b b, P = sum b a, Q = sum a b
+// (Im V = P - Q).  The two MFMAs into a Re accumulator of one 32-sample step
+// are six MFMAs apart, longer than an MFMA's latency.
 struct Acc {
-    v16i rr[2], ii[2], p[2], q[2];
+    v16i rr[2], p[2], q[2];
 };
 
 // Packed-voltage fragment of a 32-input sub-block for one 32-sample step:
@@ -129,15 +129,20 @@ __device__ __forceinline__ Frag split_frag(const RawFrag<CI4> &r) {
     return fr;
 }
 
-__device__ __forceinline__ void mfma8(const Frag &a0, const Frag &a1, const Frag &b, Acc &acc) {
-    acc.rr[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.re, acc.rr[0], 0, 0, 0);
-    acc.rr[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.re, acc.rr[1], 0, 0, 0);
-    acc.p[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.re, acc.p[0], 0, 0, 0);
-    acc.p[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.re, acc.p[1], 0, 0, 0);
-    acc.q[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.im, acc.q[0], 0, 0, 0);
-    acc.q[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.im, acc.q[1], 0, 0, 0);
-    acc.ii[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.im, acc.ii[0], 0, 0, 0);
-    acc.ii[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.im, acc.ii[1], 0, 0, 0);
+// The eight MFMAs of one 32-sample step of a 64x32 tile (row fragments a0,
+// a1, column fragment b), split for the stage's head (the first kHead) and
+// tail (the rest).
+__device__ __forceinline__ void mfma_k(int k, const Frag &a0, const Frag &a1, const Frag &b, Acc &acc) {
+    switch (k) {
+        case 0: acc.rr[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.re, acc.rr[0], 0, 0, 0); break;
+        case 1: acc.rr[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.re, acc.rr[1], 0, 0, 0); break;
+        case 2: acc.p[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.re, acc.p[0], 0, 0, 0); break;
+        case 3: acc.p[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.re, acc.p[1], 0, 0, 0); break;
+        case 4: acc.q[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.re, b.im, acc.q[0], 0, 0, 0); break;
+        case 5: acc.q[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.re, b.im, acc.q[1], 0, 0, 0); break;
+        case 6: acc.rr[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0.im, b.im, acc.rr[0], 0, 0, 0); break;
+        default: acc.rr[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1.im, b.im, acc.rr[1], 0, 0, 0); break;
+    }
 }
 
 // Raw transposing reads of one stage of a wave's 64x32 tile: per 32-sample
@@ -145,6 +150,12 @@ __device__ __forceinline__ void mfma8(const Frag &a0, const Frag &a1, const Frag
 template <bool CI4>
 struct StageRaw {
     RawFrag<CI4> r[Fmt<CI4>::kKK][3];
+};
+
+// Operands of a stage's first 32-sample step, formed from its raw reads
+// during the previous stage.
+struct StagePre {
+    Frag f[3];
 };
 
 template <bool CI4>
@@ -155,35 +166,56 @@ __device__ __forceinline__ void read_stage(const uint8_t *stage, const int (&fb)
         for (int f = 0; f < 3; ++f) raw.r[kk][f] = read_frag<CI4>(stage + fb[f], kk);
 }
 
-// MFMA work of one stage from registers.  The split of the next 32-sample step
-// is interleaved with the MFMAs of the current one.  Every MFMA is
-// unconditional (a dead sub-block of a diagonal or ragged pair is computed and
-// simply not stored): conditional MFMAs force accumulator copies at every
-// merge point.
+// MFMAs of a stage that run before its DMA and reads are issued.
+constexpr int kHead = 2;
+
+// MFMAs K0..7 of one step: the first KLEAD back to back, each later one
+// followed by a slice of the VALU work the caller placed in the same
+// scheduling region (NVALU operations in all).  A lead gives transposing
+// reads issued just before the step time to return before the VALU work that
+// consumes them stalls the MFMA issue behind it.
+template <int K0, int KLEAD, int NVALU>
+__device__ __forceinline__ void mfma_run(const Frag &a0, const Frag &a1, const Frag &b, Acc &acc) {
+#pragma unroll
+    for (int k = K0; k < 8; ++k) mfma_k(k, a0, a1, b, acc);
+    constexpr int kRest = 8 - K0 - KLEAD;
+    constexpr int kPer = (NVALU + kRest - 1) / kRest;
+    __builtin_amdgcn_sched_group_barrier(kSchedMfma, KLEAD, 0);
+#pragma unroll
+    for (int i = 0; i < kRest; ++i) {
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedValu, kPer, 0);
+    }
+}
+
+// The rest of a stage's MFMA work, from registers: the remaining MFMAs of the
+// first step, then the later steps, each step's split interleaved with the
+// MFMAs of the step before; the last step carries the split of the next
+// stage's first step (whose reads were issued after the head).  Every MFMA is
+// unconditional (a dead sub-block of a diagonal or ragged pair, or an idle
+// wave, computes values that are never stored): conditional MFMAs force
+// accumulator copies at every merge point.
 template <bool CI4>
-__device__ __forceinline__ void mfma_stage(const StageRaw<CI4> &raw, Acc &acc) {
+__device__ __forceinline__ void stage_tail(const StagePre &pre, const StageRaw<CI4> &raw,
+                                           const StageRaw<CI4> &nraw, StagePre &npre, Acc &acc) {
     constexpr int KK = Fmt<CI4>::kKK;
-    Frag cur[3];
+    constexpr int kSplitValu = CI4 ? 36 : 24;  // VALU operations of one step's split
+    static_assert(KK == 1 || KK == 2, "one or two 32-sample steps per stage");
+    if constexpr (KK == 1) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) cur[f] = split_frag<CI4>(raw.r[0][f]);
+        for (int f = 0; f < 3; ++f) npre.f[f] = split_frag<CI4>(nraw.r[0][f]);
+        mfma_run<kHead, 3, kSplitValu>(pre.f[0], pre.f[1], pre.f[2], acc);
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        Frag mid[3];
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-        Frag nxt[3];
-        if (kk + 1 < KK) {
+        for (int f = 0; f < 3; ++f) mid[f] = split_frag<CI4>(raw.r[1][f]);
+        mfma_run<kHead, 0, kSplitValu>(pre.f[0], pre.f[1], pre.f[2], acc);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int f = 0; f < 3; ++f) nxt[f] = split_frag<CI4>(raw.r[kk + 1][f]);
-        }
-        mfma8(cur[0], cur[1], cur[2], acc);
-        if (kk + 1 < KK) {
-            // 8 MFMAs, each followed by a slice of the next step's split
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(kSchedValu, 5, 0);
-            }
-#pragma unroll
-            for (int f = 0; f < 3; ++f) cur[f] = nxt[f];
-        }
+        for (int f = 0; f < 3; ++f) npre.f[f] = split_frag<CI4>(nraw.r[0][f]);
+        mfma_run<0, 2, kSplitValu>(mid[0], mid[1], mid[2], acc);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -193,42 +225,69 @@ __device__ __forceinline__ void mfma_stage(const StageRaw<CI4> &raw, Acc &acc) {
 // with i = i0 + d the element offset is tri(i0) + d*i0 + tri(d) + j: one
 // multiply-add per register from per-lane bases (32-bit: a channel holds
 // fewer than 2^31 bytes of visibilities).  Interior tiles (every element
-// inside the triangle and the array) skip the per-element test.
+// inside the triangle and the array) store without a per-element test.
+// When adding to the stored values, a sub-block's 16 old values are all
+// loaded, then added, then stored: no store waits on a load issued after an
+// earlier store (a wait for one load's data also waits for every store
+// before it).
+template <bool CI4>
+__device__ __forceinline__ void store_sub(uint8_t *obase, int irow0, int jcol0, const v16i &re, const v16i &pp,
+                                          const v16i &qq, int lane, int ninput, int overwrite) {
+    const int g = lane >> 5;
+    const int jj = jcol0 + (lane & 31);
+    const int i0 = irow0 + 4 * g;
+    const uint32_t base = (uint32_t)((i0 * (i0 + 1) / 2 + jj) * 8);
+    const uint32_t step = (uint32_t)(i0 * 8);
+    // every row >= every column and inside the array?
+    const bool interior = irow0 >= jcol0 + 31 && irow0 + 31 < ninput;
+    auto dof = [](int v) { return 8 * (v >> 2) + (v & 3); };
+    auto dst = [&](int v) {
+        const int d = dof(v);
+        return (int2 *)(obase + base + (uint32_t)d * step + (uint32_t)(d * (d + 1) / 2 * 8));
+    };
+    auto ok = [&](int v) {
+        const int i = i0 + dof(v);
+        return i < ninput && jj <= i;
+    };
+    int2 res[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        int vr = re[v];
+        int vi = pp[v] - qq[v];
+        if (CI4) { vr >>= 8; vi >>= 8; }
+        res[v] = int2{vr, vi};
+    }
+    if (!overwrite) {
+        int2 old[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            old[v] = int2{0, 0};
+            if (interior || ok(v)) old[v] = *dst(v);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) res[v] = int2{res[v].x + old[v].x, res[v].y + old[v].y};
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (interior) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) *dst(v) = res[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            if (ok(v)) *dst(v) = res[v];
+    }
+}
+
 template <bool CI4>
 __device__ __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc, int lane,
                                          int overwrite) {
-    const int ninput = it.ninput;
     uint8_t *obase = (uint8_t *)it.out + (int64_t)j.ochan * it.out_chan_bytes;
-    const int g = lane >> 5;
-    const int jj = j.cblk * kBlk + 32 * j.ch + (lane & 31);
-    const int jmax_tile = j.cblk * kBlk + 32 * j.ch + 31;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         if (!((j.live >> (2 * r + j.ch)) & 1u)) continue;
-        const int irow0 = j.rblk * kBlk + 32 * r;  // first row of the sub-block
-        const int i0 = irow0 + 4 * g;
-        const uint32_t base = (uint32_t)((i0 * (i0 + 1) / 2 + jj) * 8);
-        const uint32_t step = (uint32_t)(i0 * 8);
-        // every row >= every column and inside the array?
-        const bool interior = irow0 >= jmax_tile && irow0 + 31 < ninput;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int d = 8 * (v >> 2) + (v & 3);
-            const uint32_t off = base + (uint32_t)d * step + (uint32_t)(d * (d + 1) / 2 * 8);
-            int vr = acc.rr[r][v] + acc.ii[r][v];
-            int vi = acc.p[r][v] - acc.q[r][v];
-            if (CI4) { vr >>= 8; vi >>= 8; }
-            const int i = i0 + d;
-            if (interior || (i < ninput && jj <= i)) {
-                int2 *dst = (int2 *)(obase + off);
-                if (!overwrite) {
-                    const int2 old = *dst;
-                    vr += old.x;
-                    vi += old.y;
-                }
-                *dst = int2{vr, vi};
-            }
-        }
+        store_sub<CI4>(obase, j.rblk * kBlk + 32 * r, j.cblk * kBlk + 32 * j.ch, acc.rr[r], acc.p[r], acc.q[r],
+                       lane, it.ninput, overwrite);
     }
 }
 
@@ -236,20 +295,20 @@ __device__ inline void zero_acc(Acc &acc) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         acc.rr[r] = v16i{0};
-        acc.ii[r] = v16i{0};
         acc.p[r] = v16i{0};
         acc.q[r] = v16i{0};
     }
 }
 
 // Eight waves, two per SIMD: wave w works on 32 columns of block pair w % 4
-// (a 64x32 tile with the three accumulators of two 32x32 sub-blocks).
+// (a 64x32 tile with the four accumulators of two 32x32 sub-blocks).
 template <bool CI4>
 struct IntConsumer {
     static constexpr int kWaves = 8;
     static constexpr int kThreads = 64 * kWaves;
     typedef bfx::Acc Acc;
     typedef StageRaw<CI4> Raw;
+    typedef StagePre Pre;
     struct Bases {
         int fb[3];
     };
@@ -265,8 +324,17 @@ struct IntConsumer {
     __device__ static __forceinline__ void read(const uint8_t *st, const Bases &b, Raw &raw) {
         read_stage<CI4>(st, b.fb, raw);
     }
-    __device__ static __forceinline__ void compute(const Raw &raw, Acc &acc) {
-        mfma_stage<CI4>(raw, acc);
+    __device__ static __forceinline__ void prep(const Raw &raw, Pre &pre) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) pre.f[f] = split_frag<CI4>(raw.r[0][f]);
+    }
+    __device__ static __forceinline__ void head(const Pre &pre, const Raw &raw, Acc &acc) {
+#pragma unroll
+        for (int k = 0; k < kHead; ++k) mfma_k(k, pre.f[0], pre.f[1], pre.f[2], acc);
+    }
+    __device__ static __forceinline__ void tail(const Pre &pre, const Raw &raw, const Raw &nraw, Pre &npre,
+                                                Acc &acc) {
+        stage_tail<CI4>(pre, raw, nraw, npre, acc);
     }
     __device__ static __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc,
                                                     int lane, int overwrite) {
@@ -274,10 +342,14 @@ struct IntConsumer {
     }
 };
 
+// The consumer the integer kernels run.
 template <bool CI4>
-__global__ __launch_bounds__(IntConsumer<CI4>::kThreads, 1) void xengine_int_kernel(SingleArray w, int nt,
+using IntKernelConsumer = IntConsumer<CI4>;
+
+template <bool CI4>
+__global__ __launch_bounds__(IntKernelConsumer<CI4>::kThreads, 1) void xengine_int_kernel(SingleArray w, int nt,
                                                                   int total_flat, int overwrite) {
-    xe_loop<Fmt<CI4>, IntConsumer<CI4>>(w, nt, total_flat, overwrite);
+    xe_loop<Fmt<CI4>, IntKernelConsumer<CI4>>(w, nt, total_flat, overwrite);
 }
 
 // Work source of a batched plan: flat id B is work-list entry B, naming a
@@ -313,10 +385,10 @@ struct BatchArray {
 };
 
 template <bool CI4>
-__global__ __launch_bounds__(IntConsumer<CI4>::kThreads, 1) void xengine_batched_kernel(BatchArray w, int nt,
+__global__ __launch_bounds__(IntKernelConsumer<CI4>::kThreads, 1) void xengine_batched_kernel(BatchArray w, int nt,
                                                                       int total_flat,
                                                                       int overwrite) {
-    xe_loop<Fmt<CI4>, IntConsumer<CI4>>(w, nt, total_flat, overwrite);
+    xe_loop<Fmt<CI4>, IntKernelConsumer<CI4>>(w, nt, total_flat, overwrite);
 }
 
 int g_num_cus = 0;
@@ -369,10 +441,10 @@ hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t ncha
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
     if (ci4)
-        hipLaunchKernelGGL(xengine_int_kernel<true>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
+        hipLaunchKernelGGL(xengine_int_kernel<true>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
     else
-        hipLaunchKernelGGL(xengine_int_kernel<false>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
+        hipLaunchKernelGGL(xengine_int_kernel<false>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();
 }
@@ -392,10 +464,10 @@ hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, in
     w.bps = ci4 ? 1 : 2;
     const int64_t grid = persistent_grid(g_num_cus, nwork);
     if (ci4)
-        hipLaunchKernelGGL(xengine_batched_kernel<true>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
+        hipLaunchKernelGGL(xengine_batched_kernel<true>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
     else
-        hipLaunchKernelGGL(xengine_batched_kernel<false>, dim3((unsigned)grid), dim3(IntConsumer<true>::kThreads),
+        hipLaunchKernelGGL(xengine_batched_kernel<false>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
                            kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
     return hipGetLastError();
 }
