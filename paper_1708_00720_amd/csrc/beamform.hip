@@ -9,24 +9,36 @@
 //   W' row 2b   = (Re w_bi, -Im w_bi) over columns (2i, 2i+1),
 //   W' row 2b+1 = (Im w_bi,  Re w_bi).
 // A cf16 voltage row x[t][f][:] with (re, im) interleaved is column t of X'
-// with K contiguous: the MFMA B fragment (8 consecutive K of one column per
-// lane) is one 16-byte global load, so voltages stream from HBM into
-// registers with no LDS pass.  A cf16 weight (re in the low half, im in the
-// high half of a dword) becomes a W' element pair by flipping the sign bit of
-// the high half (row 2b) or swapping halves (row 2b+1).
+// with K contiguous, so a B fragment of v_mfma_f32_16x16x32_f16 (8
+// consecutive K of one column per lane) is 16 contiguous bytes of one row.
+// A cf16 weight (re in the low half, im in the high half of a dword) becomes
+// a W' element pair by flipping the sign bit of the high half (row 2b) or
+// swapping halves (row 2b+1).
 //
-// Tiles.  Work unit = (channel, 256 samples, 32 beams); 4 waves of 64 samples
-// (two 32-sample MFMA tiles) x 64 real rows (32 beams): v_mfma_f32_32x32x16_f16,
-// FP32 accumulation, 4 x 16 accumulators per lane.  Weights of 32 beams x 512
-// inputs (64 KiB) are staged in LDS per K chunk, rows XOR-swizzled in 16-byte
-// chunks so the A-fragment reads (8 beams per 8-lane group) are conflict free.
-// Voltage loads are double-buffered four K steps (32 inputs) ahead.
+// Data path.  Voltages reach LDS with global_load_lds_dwordx4 in stages of 16
+// samples x one K chunk of up to 256 inputs: each sample's slice of a row
+// (up to 1 KiB, contiguous in HBM) is fetched whole by consecutive lanes, so
+// every DRAM page opened is read out in one burst (loading fragments straight
+// into registers reads each row in 32-byte pieces spread over the K loop).
+// Two stages alternate; the next stage's DMA is issued behind the barrier
+// that releases the current one.  The 16-byte chunks of a row are XOR-
+// swizzled by the row index so the 16 rows of a B fragment read hit distinct
+// banks.
 //
-// Detection.  In the 32x32 output layout the (Re, Im) rows of a beam are
-// adjacent registers of one lane, so |y|^2 is lane-local; a window of navg
-// (a power of two <= 32) consecutive samples is navg consecutive lanes,
-// summed by a ds_swizzle butterfly.  Work units are assigned so that all
-// units of a channel share an XCD (its weights are read from HBM once).
+// Tiles.  Work unit = (channel, 128 samples, 32 beams); wave w owns beams
+// 8w..8w+7 (16 real MFMA rows) for all 128 samples (8 tiles of 16 samples,
+// 8 x 4 FP32 accumulators per lane).  Its W' fragments for the whole K chunk
+// (16 K steps x 8 binary16 per lane) are expanded from the cf16 weights into
+// registers once per chunk; the K loop then runs on LDS reads and MFMAs only.
+// Two workgroups share a CU.
+//
+// Detection.  In the 16x16 output layout a lane holds rows 4g..4g+3 of one
+// sample column (g = lane / 16): the (Re, Im) rows of beams 2g and 2g+1, so
+// |y|^2 is lane-local; a window of navg (a power of two <= 32) consecutive
+// samples is navg consecutive lanes of a 16-lane group (two adjacent tiles for
+// navg = 32), summed by a ds_swizzle butterfly.  Work units are assigned so
+// that all units of a channel share an XCD (its weights are read from HBM
+// once).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,20 +50,19 @@ namespace bfx {
 namespace {
 
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kBeams = 32;      // beams per unit (64 real MFMA rows)
-constexpr int kKChunk = 512;    // complex inputs per LDS weight chunk
+constexpr int kBeams = 32;      // beams per unit: 4 waves x 8 beams
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kTB = 256;        // samples per unit
-constexpr int kTWave = kTB / kWaves;  // 64 samples = 2 MFMA tiles per wave
-constexpr int kU = 4;           // K steps (8 inputs each) per load batch
-constexpr int kLdsBytes = kBeams * kKChunk * 4;  // 64 KiB
-
-// LDS byte offset of 16-byte chunk c (4 inputs) of beam row b.
-__device__ inline uint32_t w_off(int b, int c) { return (uint32_t)(b * (kKChunk * 4) + ((c ^ (b & 7)) << 4)); }
+constexpr int kS = 16;          // samples per stage (one MFMA column tile)
+constexpr int kNT = 8;          // stages per unit and K chunk
+constexpr int kTB = kS * kNT;   // samples per unit
+constexpr int kKC = 256;        // complex inputs per K chunk
+constexpr int kKS = kKC / 16;   // MFMA K steps (32 real K = 16 inputs) per chunk
+constexpr int kStageBytes = kS * kKC * 4;  // 16 KiB
+constexpr int kLdsBytes = 2 * kStageBytes;
 
 // Lane-xor exchange within 32-lane groups (ds_swizzle bitmask mode: and 0x1F,
 // or 0, xor K).
@@ -60,14 +71,13 @@ __device__ inline float swz_xor(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x1F | (K << 10)));
 }
 
-// Sum over aligned groups of 2^L consecutive lanes (L <= 5).
+// Sum over aligned groups of 2^L consecutive lanes (L <= 4).
 template <int L>
 __device__ inline float group_sum(float p) {
     if constexpr (L >= 1) p += swz_xor<1>(p);
     if constexpr (L >= 2) p += swz_xor<2>(p);
     if constexpr (L >= 3) p += swz_xor<4>(p);
     if constexpr (L >= 4) p += swz_xor<8>(p);
-    if constexpr (L >= 5) p += swz_xor<16>(p);
     return p;
 }
 
@@ -86,128 +96,136 @@ __device__ inline bool unit_of(int B, int ntb, int nbg, int nchan, Unit &u) {
     return u.f < nchan;
 }
 
-// Load the B fragments (two 32-sample tiles) of kU K steps starting at input
-// `i0` (relative to the channel row) into xb.
-__device__ __forceinline__ void load_x(v4u (&xb)[kU][2], const uint8_t *row0, const uint8_t *row1,
-                                       int i0) {
-#pragma unroll
-    for (int s = 0; s < kU; ++s) {
-        xb[s][0] = *(const v4u *)(row0 + (int64_t)(i0 + 8 * s) * 4);
-        xb[s][1] = *(const v4u *)(row1 + (int64_t)(i0 + 8 * s) * 4);
+// 16 bytes from global memory straight into LDS at m0 + 16 * lane.
+__device__ inline void dma16(const void *src, uint32_t lds_wave_base) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_wave_base)), "v"(src)
+                 : "memory", "m0");
+}
+
+// Row swizzle of the 16-byte chunks (a row of cpr chunks, cpr a multiple of 8).
+__device__ inline int row_swz(int r, int cpr) { return r & ((cpr & 15) ? 7 : 15); }
+
+// Issue this wave's share of the DMA of one stage: rows t0..t0+15 (clamped:
+// rows past ntime only feed windows that are never stored), inputs kc..kc+nin.
+__device__ __forceinline__ void stage_dma(const uint8_t *xrow0, int64_t rstride, int t0, int ntime, int nin,
+                                          uint32_t lds_stage, int wave, int lane) {
+    const int cpr = nin / 4;       // 16-byte chunks per row
+    const int ninstr = cpr / 4;    // 1 KiB wave instructions per stage (16 rows)
+    for (int j = wave; j < ninstr; j += kWaves) {
+        const int c = 64 * j + lane;
+        const int r = c / cpr;
+        const int p = c - r * cpr;
+        const int t = min(t0 + r, ntime - 1);
+        dma16(xrow0 + (int64_t)t * rstride + 16 * (p ^ row_swz(r, cpr)), lds_stage + 1024 * j);
     }
 }
 
-// kU K steps of the wave's 64 x 64 tile.  The W' fragment of row m comes
-// from the raw cf16 weights of beam m/2: row parity 0 flips the sign of the
-// imaginary halves, parity 1 swaps the halves (one v_perm + one xor per dword
-// with per-lane constants `sel`, `flip`).
-__device__ __forceinline__ void mma_batch(const v4u (&xb)[kU][2], const uint8_t *lds, int kstep0,
-                                          int brow0, int brow1, int h, uint32_t sel,
-                                          uint32_t flip, v16f (&acc)[2][2]) {
-#pragma unroll
-    for (int s = 0; s < kU; ++s) {
-        const int c = 2 * (kstep0 + s) + h;  // 16-byte chunk (4 inputs) of this lane
-        v4u a[2];
-        a[0] = *(const v4u *)(lds + w_off(brow0, c));
-        a[1] = *(const v4u *)(lds + w_off(brow1, c));
-        v8h af[2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            v4u t;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) t[q] = __builtin_amdgcn_perm(a[r][q], a[r][q], sel) ^ flip;
-            af[r] = __builtin_bit_cast(v8h, t);
-        }
-        const v8h b0 = __builtin_bit_cast(v8h, xb[s][0]);
-        const v8h b1 = __builtin_bit_cast(v8h, xb[s][1]);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[0], b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[0], b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[1], b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[1], b1, acc[1][1], 0, 0, 0);
-    }
-}
+__device__ inline void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 template <int LOGNAVG>
 __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
     const uint8_t *__restrict__ x, const uint8_t *__restrict__ w, int ninput, int nchan, int nbeam,
     int ntime, int ntb, int nbg, float *__restrict__ out) {
-    constexpr int kNavg = 1 << LOGNAVG;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
     Unit u;
     if (!unit_of(blockIdx.x, ntb, nbg, nchan, u)) return;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-    const int h = lane >> 5;      // K half of the MFMA fragment
-    const int m = lane & 31;
-    const int brow0 = m >> 1;     // beam (within the unit) of A row m, row block 0
-    const int brow1 = 16 + (m >> 1);
+    const int m = lane & 15;  // A row / B and D column of this lane
+    const int g = lane >> 4;  // K quarter of the A and B fragments; D rows 4g..4g+3
+    const int beam_a = u.bg * kBeams + 8 * wave + (m >> 1);   // beam of W' row m
     const uint32_t sel = (m & 1) ? 0x01000302u : 0x03020100u;  // swap halves / identity
     const uint32_t flip = (m & 1) ? 0u : 0x80000000u;           // negate Im w on Re rows
 
-    // this lane's two sample rows (clamped: rows past ntime only feed windows
-    // that are never stored)
-    const int tw = u.tb * kTB + wave * kTWave;
-    const int t0 = min(tw + m, ntime - 1);
-    const int t1 = min(tw + 32 + m, ntime - 1);
     const int64_t rstride = (int64_t)nchan * ninput * 4;
-    const uint8_t *xr0 = x + (int64_t)t0 * rstride + (int64_t)u.f * ninput * 4 + 16 * h;
-    const uint8_t *xr1 = x + (int64_t)t1 * rstride + (int64_t)u.f * ninput * 4 + 16 * h;
+    const int tu = u.tb * kTB;
+    const uint8_t *xf = x + (int64_t)u.f * ninput * 4;
 
-    v16f acc[2][2];
+    v4f acc[kNT];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[r][c] = v16f{0.0f};
+    for (int st = 0; st < kNT; ++st) acc[st] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
-    const int beam0 = u.bg * kBeams;
-    for (int kc = 0; kc < ninput; kc += kKChunk) {
-        const int nin = min(kKChunk, ninput - kc);  // multiple of 32
-        __syncthreads();  // the previous chunk's weights are consumed
-        // stage the weights of 32 beams x nin inputs (zero past nbeam)
-        for (int e = tid; e < kBeams * (kKChunk / 4); e += kThreads) {
-            const int b = e / (kKChunk / 4);
-            const int c = e - b * (kKChunk / 4);
-            v4u v = v4u{0u, 0u, 0u, 0u};
-            if (beam0 + b < nbeam && 4 * c < nin)
-                v = *(const v4u *)(w + (((int64_t)u.f * nbeam + beam0 + b) * ninput + kc + 4 * c) * 4);
-            *(v4u *)(lds + w_off(b, c)) = v;
-        }
+    for (int kc = 0; kc < ninput; kc += kKC) {
+        const int nin = min(kKC, ninput - kc);  // multiple of 32
+        const int nks = nin / 16;
+        const int rowb = nin * 4;               // LDS bytes per stage row
+        // every wave is done with the previous chunk's last stage
         __syncthreads();
-
-        // one batch of kU K steps per iteration; the next batch's voltages
-        // are in flight while this one is multiplied
-        const int nbatch = nin / (8 * kU);  // nin % 32 == 0
-        v4u xa[kU][2], xb[kU][2];
-        load_x(xa, xr0, xr1, kc);
-        for (int bt = 0; bt < nbatch; ++bt) {
-            if (bt + 1 < nbatch) load_x(xb, xr0, xr1, kc + (bt + 1) * 8 * kU);
-            mma_batch(xa, lds, bt * kU, brow0, brow1, h, sel, flip, acc);
+        stage_dma(xf + (int64_t)kc * 4, rstride, tu, ntime, nin, lds_base, wave, lane);
+        // W' fragments of this chunk (zero past nbeam)
+        v8h wf[kKS];
+        const uint8_t *wrow = w + (((int64_t)u.f * nbeam + beam_a) * ninput + kc + 4 * g) * 4;
 #pragma unroll
-            for (int s2 = 0; s2 < kU; ++s2) {
-                xa[s2][0] = xb[s2][0];
-                xa[s2][1] = xb[s2][1];
+        for (int ks = 0; ks < kKS; ++ks) {
+            v4u a = v4u{0u, 0u, 0u, 0u};
+            if (ks < nks && beam_a < nbeam) a = *(const v4u *)(wrow + 64 * ks);
+            v4u t;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] = __builtin_amdgcn_perm(a[q], a[q], sel) ^ flip;
+            wf[ks] = __builtin_bit_cast(v8h, t);
+        }
+        const int swz = row_swz(m, nin / 4);
+#pragma unroll
+        for (int st = 0; st < kNT; ++st) {
+            // this stage has landed everywhere, and the other slot is free
+            wait_vm0();
+            __syncthreads();
+            if (st + 1 < kNT)
+                stage_dma(xf + (int64_t)kc * 4, rstride, tu + kS * (st + 1), ntime, nin,
+                          lds_base + ((st + 1) & 1) * kStageBytes, wave, lane);
+            const uint8_t *srow = lds + (st & 1) * kStageBytes + m * rowb;
+            if (nks == kKS) {
+                // full chunk: reads in batches of eight ahead of their MFMAs
+#pragma unroll
+                for (int k0 = 0; k0 < kKS; k0 += 8) {
+                    v8h b[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        b[k] = *(const v8h *)(srow + 16 * ((4 * (k0 + k) + g) ^ swz));
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        acc[st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wf[k0 + k], b[k], acc[st], 0, 0, 0);
+                }
+            } else {
+                // partial chunk (nks even): K steps in pairs, none past nks
+#pragma unroll
+                for (int k0 = 0; k0 < kKS; k0 += 2) {
+                    if (k0 < nks) {
+                        const v8h b0 = *(const v8h *)(srow + 16 * ((4 * k0 + g) ^ swz));
+                        const v8h b1 = *(const v8h *)(srow + 16 * ((4 * k0 + 4 + g) ^ swz));
+                        acc[st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wf[k0], b0, acc[st], 0, 0, 0);
+                        acc[st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wf[k0 + 1], b1, acc[st], 0, 0, 0);
+                    }
+                }
             }
         }
     }
 
-    // detect: lane holds sample tw + 32*tt + m of beams
-    //   beam0 + 16*r + 4*(q/2) + 2*h + (q%2), from registers v = 2q, 2q+1
+    // detect: lane holds sample tu + 16*st + m of beams 8*wave + 2g (registers
+    // 0, 1) and 8*wave + 2g + 1 (registers 2, 3)
     const int nwin = ntime >> LOGNAVG;
+    const int bw = u.bg * kBeams + 8 * wave + 2 * g;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-            const int t = tw + 32 * tt + m;
-            const int uwin = t >> LOGNAVG;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float a = acc[r][tt][2 * q], b = acc[r][tt][2 * q + 1];
-                const float p = group_sum<LOGNAVG>(a * a + b * b);
-                const int beam = beam0 + 16 * r + 4 * (q >> 1) + 2 * h + (q & 1);
-                if ((m & (kNavg - 1)) == 0 && beam < nbeam && uwin < nwin)
-                    out[((int64_t)beam * nchan + u.f) * nwin + uwin] = p;
-            }
+    for (int st = 0; st < kNT; ++st) {
+        if (LOGNAVG == 5 && (st & 1)) continue;
+        float p0 = acc[st][0] * acc[st][0] + acc[st][1] * acc[st][1];
+        float p1 = acc[st][2] * acc[st][2] + acc[st][3] * acc[st][3];
+        if constexpr (LOGNAVG == 5) {
+            p0 += acc[st + 1][0] * acc[st + 1][0] + acc[st + 1][1] * acc[st + 1][1];
+            p1 += acc[st + 1][2] * acc[st + 1][2] + acc[st + 1][3] * acc[st + 1][3];
+        }
+        constexpr int L = LOGNAVG < 4 ? LOGNAVG : 4;
+        p0 = group_sum<L>(p0);
+        p1 = group_sum<L>(p1);
+        const int t = tu + kS * st + m;
+        const int uwin = t >> LOGNAVG;
+        if ((m & ((1 << L) - 1)) == 0 && uwin < nwin) {
+            if (bw < nbeam) out[((int64_t)bw * nchan + u.f) * nwin + uwin] = p0;
+            if (bw + 1 < nbeam) out[((int64_t)(bw + 1) * nchan + u.f) * nwin + uwin] = p1;
         }
     }
 }
