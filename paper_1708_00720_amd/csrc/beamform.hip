@@ -20,7 +20,7 @@
 // (up to 1 KiB, contiguous in HBM) is fetched whole by consecutive lanes, so
 // every DRAM page opened is read out in one burst (loading fragments straight
 // into registers reads each row in 32-byte pieces spread over the K loop).
-// Two stages alternate; the next stage's DMA is issued behind the barrier
+// Three stages rotate; the DMA two stages ahead is issued behind the barrier
 // that releases the current one.  The 16-byte chunks of a row are XOR-
 // swizzled by the row index so the 16 rows of a B fragment read hit distinct
 // banks.
@@ -62,7 +62,8 @@ constexpr int kTB = kS * kNT;   // samples per unit
 constexpr int kKC = 256;        // complex inputs per K chunk
 constexpr int kKS = kKC / 16;   // MFMA K steps (32 real K = 16 inputs) per chunk
 constexpr int kStageBytes = kS * kKC * 4;  // 16 KiB
-constexpr int kLdsBytes = 2 * kStageBytes;
+constexpr int kSlots = 3;       // LDS stages in flight
+constexpr int kLdsBytes = kSlots * kStageBytes;
 
 // Lane-xor exchange within 32-lane groups (ds_swizzle bitmask mode: and 0x1F,
 // or 0, xor K).
@@ -122,7 +123,21 @@ __device__ __forceinline__ void stage_dma(const uint8_t *xrow0, int64_t rstride,
     }
 }
 
-__device__ inline void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// Wait until at most N vector-memory operations of this wave are in flight
+// (N <= 15; expcnt and lgkmcnt left at their maxima).
+template <int N>
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(N | 0x0F70); }
+
+// The same with a wave-uniform run-time count n in 0..4.
+__device__ inline void wait_vm_n(int n) {
+    switch (n) {
+        case 0: wait_vm<0>(); break;
+        case 1: wait_vm<1>(); break;
+        case 2: wait_vm<2>(); break;
+        case 3: wait_vm<3>(); break;
+        default: wait_vm<4>(); break;
+    }
+}
 
 template <int LOGNAVG>
 __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
@@ -153,10 +168,10 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
         const int nin = min(kKC, ninput - kc);  // multiple of 32
         const int nks = nin / 16;
         const int rowb = nin * 4;               // LDS bytes per stage row
-        // every wave is done with the previous chunk's last stage
-        __syncthreads();
-        stage_dma(xf + (int64_t)kc * 4, rstride, tu, ntime, nin, lds_base, wave, lane);
-        // W' fragments of this chunk (zero past nbeam)
+        const int ninstr = nin / 16;            // DMA instructions per stage
+        const int nmine = wave < ninstr ? (ninstr - wave + kWaves - 1) / kWaves : 0;  // this wave's
+        // W' fragments of this chunk (zero past nbeam), complete before any
+        // DMA of the chunk is issued
         v8h wf[kKS];
         const uint8_t *wrow = w + (((int64_t)u.f * nbeam + beam_a) * ninput + kc + 4 * g) * 4;
 #pragma unroll
@@ -168,16 +183,24 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
             for (int q = 0; q < 4; ++q) t[q] = __builtin_amdgcn_perm(a[q], a[q], sel) ^ flip;
             wf[ks] = __builtin_bit_cast(v8h, t);
         }
+        // every wave is done with the previous chunk's stages
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < kSlots - 1; ++st)
+            stage_dma(xf + (int64_t)kc * 4, rstride, tu + kS * st, ntime, nin, lds_base + st * kStageBytes,
+                      wave, lane);
         const int swz = row_swz(m, nin / 4);
 #pragma unroll
         for (int st = 0; st < kNT; ++st) {
-            // this stage has landed everywhere, and the other slot is free
-            wait_vm0();
+            // this stage has landed everywhere (the next one may still be in
+            // flight), and the slot of the previous one is free
+            if (st + 1 < kNT) wait_vm_n(nmine);
+            else wait_vm<0>();
             __syncthreads();
-            if (st + 1 < kNT)
-                stage_dma(xf + (int64_t)kc * 4, rstride, tu + kS * (st + 1), ntime, nin,
-                          lds_base + ((st + 1) & 1) * kStageBytes, wave, lane);
-            const uint8_t *srow = lds + (st & 1) * kStageBytes + m * rowb;
+            if (st + kSlots - 1 < kNT)
+                stage_dma(xf + (int64_t)kc * 4, rstride, tu + kS * (st + kSlots - 1), ntime, nin,
+                          lds_base + ((st + kSlots - 1) % kSlots) * kStageBytes, wave, lane);
+            const uint8_t *srow = lds + (st % kSlots) * kStageBytes + m * rowb;
             if (nks == kKS) {
                 // full chunk: reads in batches of eight ahead of their MFMAs
 #pragma unroll
