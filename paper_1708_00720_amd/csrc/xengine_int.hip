@@ -217,6 +217,13 @@ __device__ __forceinline__ void stage_tail(const StagePre &pre, const StageRaw<C
         mfma_run<0, 2, kSplitValu>(mid[0], mid[1], mid[2], acc);
         __builtin_amdgcn_sched_barrier(0);
     }
+    // ci4: pin the next stage's operands here; otherwise the split is sunk
+    // past the loop's exit test into the next stage, in front of its first
+    // MFMAs.  (For ci8 the pinned registers cost more than the overlap gains.)
+    if constexpr (CI4) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) asm volatile("" : "+v"(npre.f[f].re), "+v"(npre.f[f].im));
+    }
 }
 
 // Store a wave's finished 64x32 tile.  32x32 output layout of

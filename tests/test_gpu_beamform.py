@@ -79,8 +79,9 @@ def test_beamform_navg(navg):
 
 @pytest.mark.parametrize("N,F,B,T,navg", [
     (32, 1, 1, 16, 16),      # smallest unit: one beam, one window
-    (544, 2, 40, 48, 16),    # two K chunks (512 + 32 inputs), two beam groups, ragged time
-    (1056, 1, 70, 272, 8),   # three K chunks, three beam groups, two time blocks + tail
+    (96, 3, 8, 64, 4),       # one partial K chunk of 24 16-byte chunks per row (not 16k)
+    (544, 2, 40, 48, 16),    # three K chunks (256 + 256 + 32 inputs), two beam groups, ragged time
+    (1056, 1, 70, 272, 8),   # five K chunks, three beam groups, two time blocks + tail
     (512, 9, 32, 512, 16),   # channel count not a multiple of 8
 ])
 def test_beamform_ragged(N, F, B, T, navg):
