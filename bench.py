@@ -163,6 +163,7 @@ def row_xengine_f16(reps, x=None):
     T, F, N = 1024, 2048, 512
     x = _cf16_block(T, F, N, 5) if x is None else x
     plan = bfx.bfx_xengine_create(N, F, "cf16")
+    tune_us = bfx.bfx_xengine_autotune(plan, T)
     acc = bfx.visibilities_buffer(plan)
     avg, med, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(plan, x, T, acc, overwrite=True), reps)
     cmac = F * T * N * (N + 1) // 2
@@ -170,7 +171,9 @@ def row_xengine_f16(reps, x=None):
     r = _row("xengine_f16_kernel", "512 inputs x 2048 channels x 1024 samples, cf16 -> cf32",
              avg, med, 8 * cmac, "flops", PEAK_FP16_TFLOPS, "TFLOP/s", "mfma", nbytes,
              {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
-              "hbm_frac_algorithmic": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)})
+              "hbm_frac_algorithmic": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+              "kernel_variant": bfx.bfx_xengine_variant(plan),
+              "autotune_us": [round(t, 1) for t in tune_us]})
     # FP64 running sum of the binary32 dump (row a5, floating-point path)
     run64 = torch.zeros(acc.numel(), dtype=torch.float64, device="cuda")
     davg, dmed, _ = time_launches(lambda: bfx.bfx_xengine_dump(plan, acc, None, run64), max(3, reps // 2))
@@ -213,6 +216,7 @@ def row_batched(reps):
     Ns = (32, 64, 96, 128, 192, 256, 384, 512)
     Fs = (1024, 512, 512, 256, 256, 128, 128, 64)
     plan = bfx.bfx_xengine_create_batched(Ns, Fs, "ci8")
+    tune_us = bfx.bfx_xengine_autotune(plan, T)
     g = torch.Generator(device="cuda").manual_seed(40)
     nin = bfx.bfx_xengine_in_bytes(plan, T)
     arena = torch.clamp(torch.round(torch.randn(nin, device="cuda", generator=g) * 8.0),
@@ -225,6 +229,7 @@ def row_batched(reps):
     alone = []
     for N, F in zip(Ns, Fs):
         p1 = bfx.bfx_xengine_create(N, F, "ci8")
+        bfx.bfx_xengine_autotune(p1, T)
         a1 = bfx.visibilities_buffer(p1)
         x1 = arena[:T * F * N * 2]
         a_avg, _, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(p1, x1, T, a1, overwrite=True), reps)
@@ -241,6 +246,8 @@ def row_batched(reps):
               "sum_standalone_us": round(sum(a["avg_launch_us"] for a in alone), 2),
               "best_standalone_hbm_frac": best,
               "batched_over_best_standalone": round(frac / best, 4),
+              "kernel_variant": bfx.bfx_xengine_variant(plan),
+              "autotune_us": [round(t, 1) for t in tune_us],
               "standalone": alone})
     plan.close()
     return r
@@ -298,6 +305,7 @@ def main():
         raw = synth.voltages(2, N_TIME, N_CHAN, N_INPUT, "ci4", 2.5, 7, gulp=0)
         d_in = torch.from_numpy(raw.reshape(-1)).to(dev)
         plan = bfx.bfx_xengine_create(N_INPUT, N_CHAN, "ci4")
+        bfx.bfx_xengine_autotune(plan, N_TIME)  # the variant the bench line times
         vis = bfx.visibilities_buffer(plan, device=dev)
         for _ in range(args.profile_launches):
             bfx.bfx_xengine_accumulate(plan, d_in, N_TIME, vis, overwrite=True)
@@ -318,6 +326,10 @@ def main():
         print(f"[bench] gulp {k} staged", file=sys.stderr, flush=True)
 
     plan = bfx.bfx_xengine_create(N_INPUT, N_CHAN, "ci4")
+    # plan setup, before any timing: pick the kernel variant for this shape
+    tune_us = bfx.bfx_xengine_autotune(plan, N_TIME)
+    variant = bfx.bfx_xengine_variant(plan)
+    print(f"[bench] autotune: variant {variant}, times {tune_us} us", file=sys.stderr, flush=True)
     vis = bfx.visibilities_buffer(plan, device=dev)
     handle = plan.handle
     lib = bfx._lib
@@ -368,6 +380,8 @@ def main():
     avg_ms = sum(durs) / len(durs)
     achieved = 8.0 * cmac_per_gulp() / (avg_ms * 1e-3) / 1e12  # TOP/s (1 CMAC = 8 int8 ops)
     roofline = {
+        "kernel_variant": variant,
+        "autotune_us": [round(t, 1) for t in tune_us],
         "kernel": "xengine_int_kernel<ci4>",
         "bound": "mfma",
         "achieved": round(achieved, 2),

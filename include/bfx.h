@@ -139,6 +139,39 @@ bfx_status bfx_xengine_sub_offsets(const bfx_xengine *plan, int32_t k, int64_t n
 /* Samples accumulated since the last BFX_ACC_OVERWRITE (host bookkeeping). */
 int64_t bfx_xengine_nacc(const bfx_xengine *plan);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel variants and autotuning (the batched persistent launch of the gulp
+ * model, Sec. 3.5, tuned per array shape).  A plan runs one of
+ * BFX_XENGINE_VARIANTS kernel variants (they differ in how the stage copies
+ * into LDS are shared among the waves); every variant computes the same
+ * result (integer paths: the same bits).
+ *
+ * bfx_xengine_autotune times each variant on the plan's shape with `ntime`
+ * samples (1 <= ntime <= min(bfx_xengine_max_ntime, 2^20)) on `stream` and
+ * keeps the fastest.  It allocates (and frees) one input gulp and one
+ * visibility buffer of device memory, waits for the stream, and leaves nacc
+ * unchanged.  times_us, if not NULL, receives the best time of each variant
+ * (host float[BFX_XENGINE_VARIANTS], microseconds).  If the environment
+ * variable BFX_TUNE_CACHE names a file, the choice is appended to it as one
+ * JSON line {"arch", "dtype", "shape", "variant", "us"}, and plans created
+ * later for the same (device architecture, dtype, shape) start with the
+ * cached variant (the last matching line wins); otherwise plans start with
+ * variant 0.  Returns BFX_EINVAL for a bad ntime, BFX_EHIP if a device
+ * allocation or launch fails (the plan keeps its variant).               */
+#define BFX_XENGINE_VARIANTS 2
+bfx_status bfx_xengine_autotune(bfx_xengine *plan, int64_t ntime, float *times_us, bfx_stream stream);
+
+/* The plan's current variant (-1 for NULL), and an explicit choice
+ * (BFX_EINVAL outside [0, BFX_XENGINE_VARIANTS)).                          */
+int32_t bfx_xengine_variant(const bfx_xengine *plan);
+bfx_status bfx_xengine_set_variant(bfx_xengine *plan, int32_t variant);
+
+/* Look up a tune-cache file without a device: the variant cached for
+ * (arch, dtype, shape), or -1 if there is none (or the file cannot be read).
+ * shape is "NxF" for a plan with N inputs and F channels, and
+ * "b:N1xF1,N2xF2,..." for a batched plan; dtype is "ci4", "ci8" or "cf16". */
+int32_t bfx_tune_cache_lookup(const char *path, const char *arch, const char *dtype, const char *shape);
+
 /* Correlate one gulp.
  *   d_in   device, [ntime][nchan][ninput] samples of the plan's dtype (for a
  *          batched plan: the input arena), 16-byte aligned;

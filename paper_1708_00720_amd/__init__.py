@@ -55,6 +55,10 @@ _SIGS = {
     "bfx_xengine_out_bytes": (_sz, [_vp]),
     "bfx_xengine_sub_offsets": (_st, [_vp, _i32, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "bfx_xengine_nacc": (_i64, [_vp]),
+    "bfx_xengine_autotune": (_st, [_vp, _i64, ctypes.POINTER(ctypes.c_float), _vp]),
+    "bfx_xengine_variant": (_i32, [_vp]),
+    "bfx_xengine_set_variant": (_st, [_vp, _i32]),
+    "bfx_tune_cache_lookup": (_i32, [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p]),
     "bfx_xengine_accumulate": (_st, [_vp, _vp, _i64, _vp, _u32, _vp]),
     "bfx_xengine_dump": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "bfx_fengine": (_st, [_vp, _i32, _i32, _i64, _vp, _vp, ctypes.c_int, _vp]),
@@ -184,6 +188,29 @@ def bfx_xengine_sub_offsets(plan: Plan, k: int, ntime: int):
 
 def bfx_xengine_nacc(plan: Plan) -> int:
     return int(_lib.bfx_xengine_nacc(plan.handle))
+
+
+BFX_XENGINE_VARIANTS = 2
+
+
+def bfx_xengine_autotune(plan: Plan, ntime: int, stream=None):
+    """Time every kernel variant on the plan's shape and keep the fastest;
+    returns the per-variant times in microseconds."""
+    times = (ctypes.c_float * BFX_XENGINE_VARIANTS)()
+    _check(_lib.bfx_xengine_autotune(plan.handle, ntime, times, _stream(stream)))
+    return [float(t) for t in times]
+
+
+def bfx_xengine_variant(plan: Plan) -> int:
+    return int(_lib.bfx_xengine_variant(plan.handle))
+
+
+def bfx_xengine_set_variant(plan: Plan, variant: int):
+    _check(_lib.bfx_xengine_set_variant(plan.handle, variant))
+
+
+def bfx_tune_cache_lookup(path: str, arch: str, dtype: str, shape: str) -> int:
+    return int(_lib.bfx_tune_cache_lookup(path.encode(), arch.encode(), dtype.encode(), shape.encode()))
 
 
 def bfx_xengine_accumulate(plan: Plan, d_in, ntime: int, d_acc, overwrite: bool = True,

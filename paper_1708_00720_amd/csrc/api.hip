@@ -6,10 +6,12 @@
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "bfx_internal.h"
@@ -33,7 +35,7 @@ bfx_status hip_fail(hipError_t e, const char *what) {
 
 // Defined with the kernels.
 hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
-                              float *out, bool overwrite, hipStream_t s);
+                              float *out, bool overwrite, int variant, hipStream_t s);
 hipError_t launch_dump(bool is_int, const void *acc, void *out, double *run64, int64_t n,
                        hipStream_t s);
 hipError_t launch_fengine(const int8_t *in, int32_t ninput, int32_t nfft, int64_t nspec,
@@ -57,6 +59,7 @@ struct bfx_xengine {
     bool batched;
     std::vector<Sub> subs;
     int64_t nacc;
+    int variant;  // kernel variant (bfx_xengine_autotune)
     // batched plans only: device unit table and work list
     BatchUnit *d_units;
     int2 *d_work;
@@ -173,6 +176,88 @@ int64_t bfx_xengine_max_ntime(bfx_dtype in) {
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---- autotuning: the kernel variant of a plan, chosen by timing, optionally
+// remembered in a cache file of JSON lines
+//   {"arch": "gfx950", "dtype": "ci4", "shape": "704x192", "variant": 0, "us": [233.1, 241.7]}
+// keyed by (arch, dtype, shape); the last matching line wins.
+
+const char *dtype_name(bfx_dtype d) {
+    switch (d) {
+        case BFX_CI4: return "ci4";
+        case BFX_CI8: return "ci8";
+        case BFX_CF16: return "cf16";
+        default: return "?";
+    }
+}
+
+// "ninput x nchan" of every subarray, "," separated ("b:" prefix when batched).
+std::string shape_key(const bfx_xengine *p) {
+    std::string k = p->batched ? "b:" : "";
+    for (size_t i = 0; i < p->subs.size(); ++i) {
+        if (i) k += ",";
+        k += std::to_string(p->subs[i].ninput) + "x" + std::to_string(p->subs[i].nchan);
+    }
+    return k;
+}
+
+// The string value of "key": "..." in a cache line, or "" if absent.
+std::string json_str(const std::string &line, const char *key) {
+    const std::string pat = std::string("\"") + key + "\": \"";
+    const size_t a = line.find(pat);
+    if (a == std::string::npos) return "";
+    const size_t b = line.find('"', a + pat.size());
+    if (b == std::string::npos) return "";
+    return line.substr(a + pat.size(), b - a - pat.size());
+}
+
+int lookup_variant(const char *path, const std::string &arch, const std::string &dtype,
+                   const std::string &shape) {
+    FILE *f = path ? fopen(path, "r") : nullptr;
+    if (!f) return -1;
+    int found = -1;
+    char buf[8192];
+    while (fgets(buf, sizeof buf, f)) {
+        const std::string line(buf);
+        if (json_str(line, "arch") != arch || json_str(line, "dtype") != dtype ||
+            json_str(line, "shape") != shape)
+            continue;
+        const size_t a = line.find("\"variant\": ");
+        if (a == std::string::npos) continue;
+        const int v = atoi(line.c_str() + a + 11);
+        if (v >= 0 && v < kXengineVariants) found = v;
+    }
+    fclose(f);
+    return found;
+}
+
+// Name of the current device's architecture ("" when there is no device).
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Variant for a new plan: the cache's entry for it, else 0.
+int cached_variant(const bfx_xengine *p) {
+    const char *path = getenv("BFX_TUNE_CACHE");
+    if (!path || !*path) return 0;
+    const std::string arch = device_arch();
+    if (arch.empty()) return 0;
+    const int v = lookup_variant(path, arch, dtype_name(p->in), shape_key(p));
+    return v < 0 ? 0 : v;
+}
+
+}  // namespace
+
+extern "C" {
+
 bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan, bfx_dtype in) {
     g_detail[0] = 0;
     if (!plan) return fail(BFX_EINVAL, "plan pointer is NULL");
@@ -190,6 +275,7 @@ bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan,
     p->d_units = nullptr;
     p->d_work = nullptr;
     p->nwork = 0;
+    p->variant = cached_variant(p);
     *plan = p;
     return BFX_OK;
 }
@@ -237,7 +323,7 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
     hipError_t e = hipMalloc((void **)&p->d_units, units.size() * sizeof(BatchUnit));
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_work, work.size() * sizeof(int2));
     if (e != hipSuccess) {
-        hipFree(p->d_units);
+        (void)hipFree(p->d_units);
         delete p;
         return fail(BFX_ENOMEM, "device allocation of the work list failed: %s",
                     hipGetErrorString(e));
@@ -247,11 +333,12 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
     if (e == hipSuccess)
         e = hipMemcpy(p->d_work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        hipFree(p->d_units);
-        hipFree(p->d_work);
+        (void)hipFree(p->d_units);
+        (void)hipFree(p->d_work);
         delete p;
         return hip_fail(e, "copying the work list");
     }
+    p->variant = cached_variant(p);
     *plan = p;
     return BFX_OK;
 }
@@ -305,6 +392,99 @@ bfx_status bfx_xengine_sub_offsets(const bfx_xengine *plan, int32_t k, int64_t n
 
 int64_t bfx_xengine_nacc(const bfx_xengine *plan) { return plan ? plan->nacc : -1; }
 
+int32_t bfx_xengine_variant(const bfx_xengine *plan) { return plan ? plan->variant : -1; }
+
+bfx_status bfx_xengine_set_variant(bfx_xengine *plan, int32_t variant) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan is NULL");
+    if (variant < 0 || variant >= kXengineVariants)
+        return fail(BFX_EINVAL, "variant %d out of range [0, %d)", variant, kXengineVariants);
+    plan->variant = variant;
+    return BFX_OK;
+}
+
+int32_t bfx_tune_cache_lookup(const char *path, const char *arch, const char *dtype, const char *shape) {
+    if (!path || !arch || !dtype || !shape) return -1;
+    return lookup_variant(path, arch, dtype, shape);
+}
+
+bfx_status bfx_xengine_autotune(bfx_xengine *plan, int64_t ntime, float *times_us, bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan is NULL");
+    const int64_t tmax = bfx_xengine_max_ntime(plan->in);
+    if (ntime <= 0 || ntime > tmax || ntime > ((int64_t)1 << 20))
+        return fail(BFX_EINVAL, "ntime=%lld must be in [1, min(%lld, 2^20)]", (long long)ntime,
+                    (long long)tmax);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t in_bytes = bfx_xengine_in_bytes(plan, ntime);
+    const size_t out_bytes = bfx_xengine_out_bytes(plan);
+    void *d_in = nullptr, *d_acc = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc(&d_in, in_bytes);
+    if (e == hipSuccess) e = hipMalloc(&d_acc, out_bytes);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    // any bit pattern is a valid ci4 / ci8 sample; 0x3C bytes are a finite cf16 value
+    if (e == hipSuccess) e = hipMemsetAsync(d_in, 0x3C, in_bytes, s);
+    const int saved = plan->variant;
+    const int64_t saved_nacc = plan->nacc;
+    float us[kXengineVariants] = {};
+    float best_ms = 0.0f;
+    int best = 0;
+    bfx_status st = BFX_OK;
+    for (int v = 0; v < kXengineVariants && e == hipSuccess && st == BFX_OK; ++v) {
+        plan->variant = v;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 4 && e == hipSuccess && st == BFX_OK; ++rep) {
+            // the first run warms up; the fastest of the other three counts
+            if (rep > 0) e = hipEventRecord(ev[0], s);
+            if (e != hipSuccess) break;
+            st = bfx_xengine_accumulate(plan, d_in, ntime, d_acc, BFX_ACC_OVERWRITE, stream);
+            if (st != BFX_OK || rep == 0) continue;
+            e = hipEventRecord(ev[1], s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (e == hipSuccess && (rep == 1 || t < ms)) ms = t;
+        }
+        if (e == hipSuccess && st == BFX_OK) {
+            us[v] = ms * 1000.0f;
+            if (times_us) times_us[v] = us[v];
+            if (v == 0 || ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_in);
+    (void)hipFree(d_acc);
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    plan->nacc = saved_nacc;
+    if (st != BFX_OK) {
+        plan->variant = saved;
+        return st;
+    }
+    if (e != hipSuccess) {
+        plan->variant = saved;
+        return hip_fail(e, "autotuning");
+    }
+    plan->variant = best;
+    const char *path = getenv("BFX_TUNE_CACHE");
+    if (path && *path) {
+        FILE *f = fopen(path, "a");
+        if (!f) return fail(BFX_EINVAL, "cannot append to the tune cache %s", path);
+        fprintf(f, "{\"arch\": \"%s\", \"dtype\": \"%s\", \"shape\": \"%s\", \"variant\": %d, \"us\": [",
+                device_arch().c_str(), dtype_name(plan->in), shape_key(plan).c_str(), best);
+        for (int v = 0; v < kXengineVariants; ++v)
+            fprintf(f, "%s%.1f", v ? ", " : "", us[v]);
+        fprintf(f, "]}\n");
+        fclose(f);
+    }
+    return BFX_OK;
+}
+
 bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t ntime, void *d_acc,
                                   uint32_t flags, bfx_stream stream) {
     g_detail[0] = 0;
@@ -332,7 +512,7 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
             const int64_t nt = ntime - t0 < kLaunchMaxTime ? ntime - t0 : kLaunchMaxTime;
             const uint8_t *src = (const uint8_t *)d_in + t0 * sb.nchan * sb.ninput * 4;
             e = launch_xengine_f16(src, nt, sb.nchan, sb.ninput, (float *)d_acc,
-                                   overwrite && t0 == 0, s);
+                                   overwrite && t0 == 0, plan->variant, s);
         }
     } else {
         const bool ci4 = plan->in == BFX_CI4;
@@ -346,10 +526,11 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
                 const Sub &sb = plan->subs[0];
                 const uint8_t *src =
                     (const uint8_t *)d_in + t0 * sb.nchan * sb.ninput * row_bytes_per_input;
-                e = launch_xengine_int(ci4, src, nt, sb.nchan, sb.ninput, (int32_t *)d_acc, ow, s);
+                e = launch_xengine_int(ci4, src, nt, sb.nchan, sb.ninput, (int32_t *)d_acc, ow,
+                                       plan->variant, s);
             } else {
                 e = launch_xengine_batched(ci4, d_in, ntime, t0, nt, plan->d_units, plan->d_work,
-                                           plan->nwork, d_acc, ow, s);
+                                           plan->nwork, d_acc, ow, plan->variant, s);
             }
         }
     }

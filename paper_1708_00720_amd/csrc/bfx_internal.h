@@ -19,8 +19,11 @@ constexpr int64_t kLaunchMaxTime = 65535;
 // Integer X-engine (ci4 / ci8 -> int32 packed lower triangle) over one
 // contiguous array.  `in` points at time row t0 of a [t][nchan][ninput] gulp,
 // `nt` <= kLaunchMaxTime rows follow.  `overwrite` stores V, else adds.
+// Kernel variants of the X-engines (0: four DMA waves, 1: eight).
+constexpr int kXengineVariants = 2;
+
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan,
-                              int32_t ninput, int32_t *out, bool overwrite, hipStream_t s);
+                              int32_t ninput, int32_t *out, bool overwrite, int variant, hipStream_t s);
 
 // Per-subarray record of a batched plan (device table, built at plan
 // creation).  Subarray k's gulp of ntime samples starts at byte
@@ -53,6 +56,6 @@ int64_t xengine_items(int32_t ninput, int32_t nchan);
 // subarray's gulp of ntime samples.
 hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, int64_t t0,
                                   int64_t nt, const BatchUnit *d_units, const int2 *d_work,
-                                  int64_t nwork, void *out, bool overwrite, hipStream_t s);
+                                  int64_t nwork, void *out, bool overwrite, int variant, hipStream_t s);
 
 }  // namespace bfx

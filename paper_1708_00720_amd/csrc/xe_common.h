@@ -418,8 +418,10 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // (read completely by every wave before the barrier) is refilled and the
 // reads of stage s+1 are issued; the remaining MFMAs of stage s then cover
 // those reads and the forming of stage s+1's first operands.  Only the first
-// kDmaWaves waves (one per SIMD) issue DMA: the other wave of each SIMD goes
-// straight on to its MFMAs while its partner does the producer's work.  At an item's last stage the
+// kDmaWaves waves issue DMA.  With four (one per SIMD) the other wave of each
+// SIMD goes straight on to its MFMAs while its partner does the producer's
+// work; with eight every wave takes a smaller share.  Which is faster depends
+// on the shape, so the plan picks (see the autotuner in the host API).  At an item's last stage the
 // next item's job is decoded first, so its first stage is read under the same
 // overlap.  The loop body runs twice per trip with the two register sets
 // swapped, so no operand is copied.
@@ -429,7 +431,7 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // the awaited stage, is therefore exact for the loads whatever the stores do:
 // while the awaited DMA is outstanding so is every later load, so at least
 // N + 1 operations are.  Pending stores can only lengthen the wait.
-template <class F, class C, class W>
+template <class F, class C, int DMA_WAVES, class W>
 __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int overwrite) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
@@ -437,7 +439,7 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
     const int lane = tid & 63;
-    constexpr int kDmaWaves = 4;
+    constexpr int kDmaWaves = DMA_WAVES;
     static_assert(C::kWaves % kDmaWaves == 0, "DMA waves spread over the SIMDs");
     const bool dma_wave = wave < kDmaWaves;
     const int dw = wave;  // DMA waves issue DPW of each stage's DMA each

@@ -195,10 +195,15 @@ struct F16Consumer {
     }
 };
 
+template <int DW>
 __global__ __launch_bounds__(F16Consumer::kThreads, 1) void xengine_f16_kernel(SingleArray w, int nt,
                                                                   int total_flat, int overwrite) {
-    xe_loop<F16Fmt, F16Consumer>(w, nt, total_flat, overwrite);
+    xe_loop<F16Fmt, F16Consumer, DW>(w, nt, total_flat, overwrite);
 }
+
+// Kernel variants a plan chooses between (index = variant).
+typedef void (*F16Kernel)(SingleArray, int, int, int);
+const F16Kernel kF16[kXengineVariants] = {xengine_f16_kernel<4>, xengine_f16_kernel<8>};
 
 int g_num_cus = 0;
 std::once_flag g_init_once;
@@ -212,14 +217,18 @@ void init_once() {
     g_init_err = hipGetDeviceProperties(&prop, dev);
     if (g_init_err != hipSuccess) return;
     g_num_cus = prop.multiProcessorCount;
-    g_init_err = hipFuncSetAttribute((const void *)xengine_f16_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    for (int v = 0; v < kXengineVariants; ++v) {
+        g_init_err = hipFuncSetAttribute((const void *)kF16[v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kLdsBytes);
+        if (g_init_err != hipSuccess) return;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
-                              float *out, bool overwrite, hipStream_t s) {
+                              float *out, bool overwrite, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
     std::call_once(g_init_once, init_once);
     if (g_init_err != hipSuccess) return g_init_err;
     SingleArray w;
@@ -236,7 +245,7 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     w.ngroups = (nchan + w.npk - 1) / w.npk;
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
-    hipLaunchKernelGGL(xengine_f16_kernel, dim3((unsigned)grid), dim3(F16Consumer::kThreads), kLdsBytes, s, w,
+    hipLaunchKernelGGL(kF16[variant], dim3((unsigned)grid), dim3(F16Consumer::kThreads), kLdsBytes, s, w,
                        (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();
 }

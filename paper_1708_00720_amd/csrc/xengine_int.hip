@@ -353,10 +353,10 @@ struct IntConsumer {
 template <bool CI4>
 using IntKernelConsumer = IntConsumer<CI4>;
 
-template <bool CI4>
+template <bool CI4, int DW>
 __global__ __launch_bounds__(IntKernelConsumer<CI4>::kThreads, 1) void xengine_int_kernel(SingleArray w, int nt,
                                                                   int total_flat, int overwrite) {
-    xe_loop<Fmt<CI4>, IntKernelConsumer<CI4>>(w, nt, total_flat, overwrite);
+    xe_loop<Fmt<CI4>, IntKernelConsumer<CI4>, DW>(w, nt, total_flat, overwrite);
 }
 
 // Work source of a batched plan: flat id B is work-list entry B, naming a
@@ -391,12 +391,23 @@ struct BatchArray {
     }
 };
 
-template <bool CI4>
+template <bool CI4, int DW>
 __global__ __launch_bounds__(IntKernelConsumer<CI4>::kThreads, 1) void xengine_batched_kernel(BatchArray w, int nt,
                                                                       int total_flat,
                                                                       int overwrite) {
-    xe_loop<Fmt<CI4>, IntKernelConsumer<CI4>>(w, nt, total_flat, overwrite);
+    xe_loop<Fmt<CI4>, IntKernelConsumer<CI4>, DW>(w, nt, total_flat, overwrite);
 }
+
+// Kernel variants a plan chooses between (index = variant): the number of
+// waves that issue the stage DMA.
+typedef void (*SingleKernel)(SingleArray, int, int, int);
+typedef void (*BatchKernel)(BatchArray, int, int, int);
+const SingleKernel kSingle[2][kXengineVariants] = {
+    {xengine_int_kernel<false, 4>, xengine_int_kernel<false, 8>},
+    {xengine_int_kernel<true, 4>, xengine_int_kernel<true, 8>}};
+const BatchKernel kBatched[2][kXengineVariants] = {
+    {xengine_batched_kernel<false, 4>, xengine_batched_kernel<false, 8>},
+    {xengine_batched_kernel<true, 4>, xengine_batched_kernel<true, 8>}};
 
 int g_num_cus = 0;
 std::once_flag g_init_once;
@@ -410,16 +421,15 @@ void init_once() {
     g_init_err = hipGetDeviceProperties(&prop, dev);
     if (g_init_err != hipSuccess) return;
     g_num_cus = prop.multiProcessorCount;
-    g_init_err = hipFuncSetAttribute((const void *)xengine_int_kernel<true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (g_init_err != hipSuccess) return;
-    const void *kernels[3] = {(const void *)xengine_int_kernel<false>,
-                              (const void *)xengine_batched_kernel<true>,
-                              (const void *)xengine_batched_kernel<false>};
-    for (const void *k : kernels) {
-        g_init_err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-        if (g_init_err != hipSuccess) return;
-    }
+    for (int c = 0; c < 2; ++c)
+        for (int v = 0; v < kXengineVariants; ++v) {
+            g_init_err = hipFuncSetAttribute((const void *)kSingle[c][v],
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            if (g_init_err != hipSuccess) return;
+            g_init_err = hipFuncSetAttribute((const void *)kBatched[c][v],
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            if (g_init_err != hipSuccess) return;
+        }
 }
 
 }  // namespace
@@ -430,7 +440,8 @@ int64_t xengine_items(int32_t ninput, int32_t nchan) {
 }
 
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan, int32_t ninput,
-                              int32_t *out, bool overwrite, hipStream_t s) {
+                              int32_t *out, bool overwrite, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
     std::call_once(g_init_once, init_once);
     if (g_init_err != hipSuccess) return g_init_err;
     SingleArray w;
@@ -447,18 +458,15 @@ hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t ncha
     w.ngroups = (nchan + w.npk - 1) / w.npk;
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(g_num_cus, total_flat);
-    if (ci4)
-        hipLaunchKernelGGL(xengine_int_kernel<true>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
-                           kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
-    else
-        hipLaunchKernelGGL(xengine_int_kernel<false>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
-                           kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
+    hipLaunchKernelGGL(kSingle[ci4][variant], dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
+                       kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();
 }
 
 hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, int64_t t0,
                                   int64_t nt, const BatchUnit *d_units, const int2 *d_work,
-                                  int64_t nwork, void *out, bool overwrite, hipStream_t s) {
+                                  int64_t nwork, void *out, bool overwrite, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
     std::call_once(g_init_once, init_once);
     if (g_init_err != hipSuccess) return g_init_err;
     BatchArray w;
@@ -470,12 +478,8 @@ hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, in
     w.t0 = t0;
     w.bps = ci4 ? 1 : 2;
     const int64_t grid = persistent_grid(g_num_cus, nwork);
-    if (ci4)
-        hipLaunchKernelGGL(xengine_batched_kernel<true>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
-                           kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
-    else
-        hipLaunchKernelGGL(xengine_batched_kernel<false>, dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
-                           kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
+    hipLaunchKernelGGL(kBatched[ci4][variant], dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
+                       kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
     return hipGetLastError();
 }
 
