@@ -120,3 +120,13 @@ def test_beamform_full_size_sampled(cf16_full):
     chans = [0, 7, 8, 1023, 2047]
     _check(got[:, chans], np.ascontiguousarray(x[:, chans]), np.ascontiguousarray(w[chans]), navg,
            "full size, 5 channels")
+
+
+def test_beamform_max_inputs_and_beams():
+    """ninput = 8192 (32 K chunks) and nbeam = 256 (8 beam groups), the API
+    maxima, with navg = 32."""
+    N, F, B, T, navg = 8192, 2, 256, 64, 32
+    banner(f"beamform max N={N} F={F} B={B} T={T} navg={navg}")
+    x = synth.cf16_voltages(81, T, F, N)
+    w = synth.steering_weights(82, F, B, N)
+    _check(_run(x, w, N, F, B, T, navg), x, w, navg, "max sizes")

@@ -188,3 +188,14 @@ def test_items_span_several_rounds(dtype, T):
     want = oracle.xengine_int(raw, dtype, T, F, N)
     bad = np.nonzero(np.any(got != want, axis=(1, 2)))[0]
     assert bad.size == 0, f"{bad.size} channels differ, first {bad[:8].tolist()}"
+
+
+def test_max_ninput_ci8():
+    """The largest array the API takes (8192 inputs = 128 blocks, 2080 items of
+    one channel), with a ragged time count: bit-exact against the oracle."""
+    T, F, N = 40, 1, 8192
+    banner(f"xengine ci8 max inputs T={T} F={F} N={N}")
+    raw = synth.voltages(8192, T, F, N, "ci8", 8.0, 127)
+    got = packed_vis(_run(raw, "ci8", T, F, N), F, N)
+    want = oracle.xengine_int(raw, "ci8", T, F, N)
+    assert np.array_equal(got, want)
