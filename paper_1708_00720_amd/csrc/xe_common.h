@@ -132,9 +132,18 @@ __device__ inline void decode_packed(int npack, Task &tk) {
 }
 
 // Select element k of a 4-element task array without dynamic indexing (which
-// would place the array in scratch or LDS).
+// would place the array in scratch or LDS).  For a wave-uniform k.
 __device__ inline int pick4(const int (&a)[4], int k) {
     return k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+}
+
+// The same for a per-lane k, in bit operations only: a chain of conditional
+// selects here is turned into divergent branches by the compiler.
+__device__ inline int lane_pick4(const int (&a)[4], int k) {
+    const int m1 = -(k & 1), m2 = -((k >> 1) & 1);
+    const int lo = a[0] ^ ((a[0] ^ a[1]) & m1);
+    const int hi = a[2] ^ ((a[2] ^ a[3]) & m1);
+    return lo ^ ((lo ^ hi) & m2);
 }
 
 __device__ inline uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
@@ -311,7 +320,7 @@ __device__ __forceinline__ void prod_item(Producer<DPW> &P, int dw, int lane) {
     for (int ii = 0; ii < DPW; ++ii) {
         int row, slot, inp0;
         dma_geom<F, DPW>(dw, ii, lane, row, slot, inp0);
-        const int blk = pick4(tk.blk, slot);
+        const int blk = lane_pick4(tk.blk, slot);
         const int inp = blk * kBlk + inp0;
         const bool ok = blk >= 0 && inp < P.it.ninput;
         P.okmask |= ok ? (1 << ii) : 0;
@@ -319,9 +328,10 @@ __device__ __forceinline__ void prod_item(Producer<DPW> &P, int dw, int lane) {
         // fetches input 0 of the same row instead: such LDS inputs only feed
         // outputs that are never stored (every output depends on its own two
         // inputs alone), so no zero fill is needed -- except past the last
-        // time row, which the slow path zero-fills.
-        P.d_off[ii] = (int64_t)row * P.it.t_stride +
-                      (ok ? (int64_t)pick4(tk.chan, slot) * P.it.chan_bytes + (int64_t)inp * F::kBps : 0);
+        // time row, which the slow path zero-fills.  The offset is masked,
+        // not selected, so that no lane takes a branch.
+        const int64_t off = (int64_t)lane_pick4(tk.chan, slot) * P.it.chan_bytes + (int64_t)inp * F::kBps;
+        P.d_off[ii] = (int64_t)row * P.it.t_stride + (off & -(int64_t)ok);
         P.inp[ii] = inp;
     }
     P.row = P.it.base;

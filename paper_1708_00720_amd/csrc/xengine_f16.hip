@@ -161,18 +161,20 @@ struct F16Consumer {
                 float2 res[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float send0 = odd ? v[4 * s] : v[4 * s + 2];
-                    const float send1 = odd ? v[4 * s + 1] : v[4 * s + 3];
-                    const float keep0 = odd ? v[4 * s + 2] : v[4 * s];
-                    const float keep1 = odd ? v[4 * s + 3] : v[4 * s + 1];
-                    const float recv0 = swap_lane(send0);
-                    const float recv1 = swap_lane(send1);
-                    // even lane: Re = C[re][re] (keep0) + C[im][im] (recv1),
-                    //            Im = C[im][re] (keep1) - C[re][im] (recv0);
-                    // odd lane:  Re = C[re][re] (recv0) + C[im][im] (keep1),
-                    //            Im = C[im][re] (recv1) - C[re][im] (keep0).
-                    res[s] = float2{(odd ? recv0 : keep0) + (odd ? keep1 : recv1),
-                                    (odd ? recv1 : keep1) - (odd ? keep0 : recv0)};
+                    // a_k: this lane's register 4s+k; b_k: the same register
+                    // of the neighbouring lane.  Registers 4s, 4s+1 are the
+                    // even complex row's real row, 4s+2, 4s+3 the next real
+                    // row; even lanes hold real column 2j, odd lanes 2j+1.
+                    //   even lane (row 2i'):   Re = a0 + b1, Im = a1 - b0;
+                    //   odd lane (row 2i'+1):  Re = b2 + a3, Im = b3 - a2.
+                    // Both are formed and the lane keeps its own: a select
+                    // between the registers themselves would become a
+                    // per-lane indexed read of the accumulator vector.
+                    const float a0 = v[4 * s], a1 = v[4 * s + 1], a2 = v[4 * s + 2], a3 = v[4 * s + 3];
+                    const float b0 = swap_lane(a0), b1 = swap_lane(a1), b2 = swap_lane(a2), b3 = swap_lane(a3);
+                    const float ere = a0 + b1, eim = a1 - b0;
+                    const float ore = b2 + a3, oim = b3 - a2;
+                    res[s] = float2{odd ? ore : ere, odd ? oim : eim};
                 }
                 if (!overwrite) {
                     // all old values first, then the sums, then the stores
