@@ -440,7 +440,8 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // order.  A wait for "at most N outstanding", N = the DMA loads issued after
 // the awaited stage, is therefore exact for the loads whatever the stores do:
 // while the awaited DMA is outstanding so is every later load, so at least
-// N + 1 operations are.  Pending stores can only lengthen the wait.
+// N + 1 operations are.  Pending stores can only lengthen the wait, and
+// waves that issue no DMA do not wait on the counter at all.
 template <class F, class C, int DMA_WAVES, class W>
 __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int overwrite) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -494,7 +495,7 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     if (dma_wave)
         for (int k = 0; k < kRing - 1; ++k)
             prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
-    wait_vm<kAhead>();
+    if (dma_wave) wait_vm<kAhead>();
     block_barrier();
     if (dma_wave) prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     C::read(lds, fb, ra);
@@ -526,7 +527,7 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
         if (more) {
             // every read of stage s has returned: its slot may be refilled
             wait_lds();
-            wait_vm<kAhead>();
+            if (dma_wave) wait_vm<kAhead>();
             block_barrier();
         }
         C::head(pcur, cur, acc);
