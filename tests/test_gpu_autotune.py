@@ -15,7 +15,9 @@ from gpu_util import banner, packed_vis, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _acc_variants(plan, d_in, T, nvar):
+def _acc_variants(plan, d_in, T, nvar, twice=False):
+    """Each variant's visibilities after one overwrite launch (and, with
+    twice, a second, accumulating launch on the same input)."""
     import torch
     import paper_1708_00720_amd as bfx
     outs = []
@@ -23,6 +25,8 @@ def _acc_variants(plan, d_in, T, nvar):
         bfx.bfx_xengine_set_variant(plan, v)
         acc = bfx.visibilities_buffer(plan)
         bfx.bfx_xengine_accumulate(plan, d_in, T, acc, overwrite=True)
+        if twice:
+            bfx.bfx_xengine_accumulate(plan, d_in, T, acc, overwrite=False)
         torch.cuda.synchronize()
         outs.append(acc.cpu().numpy().copy())
     return outs
@@ -30,23 +34,26 @@ def _acc_variants(plan, d_in, T, nvar):
 
 @pytest.mark.parametrize("dtype", ["ci4", "ci8"])
 def test_int_variants_bit_exact(dtype):
+    import torch
     import paper_1708_00720_amd as bfx
-    T, F, N = 200, 5, 132
+    T, F, N = 200, 40, 132
     banner(f"variants {dtype} T={T} F={F} N={N}")
     raw = synth.extreme_voltages(77, T, F, N, dtype)
     plan = bfx.bfx_xengine_create(N, F, dtype)
-    outs = _acc_variants(plan, to_dev(raw), T, bfx.BFX_XENGINE_VARIANTS)
     want = oracle.xengine_int(raw, dtype, T, F, N)
+    outs = _acc_variants(plan, to_dev(raw), T, bfx.BFX_XENGINE_VARIANTS)
     for v, o in enumerate(outs):
-        import torch
-        got = packed_vis(torch.from_numpy(o), F, N)
-        assert np.array_equal(got, want), f"variant {v}"
+        assert np.array_equal(packed_vis(torch.from_numpy(o), F, N), want), f"variant {v}"
+    # overwrite, then accumulate onto it
+    outs = _acc_variants(plan, to_dev(raw), T, bfx.BFX_XENGINE_VARIANTS, twice=True)
+    for v, o in enumerate(outs):
+        assert np.array_equal(packed_vis(torch.from_numpy(o), F, N), 2 * want), f"variant {v} twice"
     plan.close()
 
 
 def test_f16_variants_identical():
     import paper_1708_00720_amd as bfx
-    T, F, N = 96, 3, 100
+    T, F, N = 96, 24, 100
     banner(f"variants cf16 T={T} F={F} N={N}")
     x = synth.cf16_voltages(5, T, F, N)
     plan = bfx.bfx_xengine_create(N, F, "cf16")
@@ -59,7 +66,7 @@ def test_f16_variants_identical():
 def test_batched_variants_bit_exact():
     import paper_1708_00720_amd as bfx
     T = 77
-    Ns, Fs = (36, 100, 68), (2, 3, 4)
+    Ns, Fs = (36, 100, 68), (6, 20, 12)
     banner(f"variants batched ci8 T={T}")
     plan = bfx.bfx_xengine_create_batched(Ns, Fs, "ci8")
     arena = np.zeros(bfx.bfx_xengine_in_bytes(plan, T), dtype=np.uint8)
