@@ -257,15 +257,15 @@ typedef void (*BfKernel)(const uint8_t *, const uint8_t *, int, int, int, int, i
 const BfKernel kKernels[6] = {beamform_kernel<0>, beamform_kernel<1>, beamform_kernel<2>,
                               beamform_kernel<3>, beamform_kernel<4>, beamform_kernel<5>};
 
-std::once_flag g_init_once;
-hipError_t g_init_err = hipSuccess;
+DeviceInit g_init;
 
-void init_once() {
+hipError_t set_attributes() {
     for (BfKernel k : kKernels) {
-        g_init_err = hipFuncSetAttribute((const void *)k,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-        if (g_init_err != hipSuccess) return;
+        const hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kLdsBytes);
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -274,8 +274,8 @@ bool beamform_supported(int32_t navg) { return navg >= 1 && navg <= 32 && (navg 
 
 hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t nchan,
                            int32_t nbeam, int64_t ntime, int32_t navg, float *out, hipStream_t s) {
-    std::call_once(g_init_once, init_once);
-    if (g_init_err != hipSuccess) return g_init_err;
+    const hipError_t e = g_init.ensure(set_attributes, nullptr);
+    if (e != hipSuccess) return e;
     int lognavg = 0;
     while ((1 << lognavg) < navg) ++lognavg;
     const int ntb = (int)((ntime + kTB - 1) / kTB);

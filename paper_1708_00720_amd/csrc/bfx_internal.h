@@ -3,9 +3,41 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/bfx.h"
 
 namespace bfx {
+
+// One-time set-up of a kernel family, per device: `init` (kernel attributes,
+// device tables) runs under the lock the first time a launch finds device d
+// current, and is retried on a later call if it failed.  ensure() also
+// returns the current device's compute-unit count.
+constexpr int kMaxDevices = 64;
+struct DeviceInit {
+    std::mutex mu;
+    bool ready[kMaxDevices] = {};
+    int cus[kMaxDevices] = {};
+    template <class Fn>
+    hipError_t ensure(Fn &&init, int *num_cus) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+        std::lock_guard<std::mutex> lk(mu);
+        if (!ready[dev]) {
+            hipDeviceProp_t prop;
+            e = hipGetDeviceProperties(&prop, dev);
+            if (e != hipSuccess) return e;
+            e = init();
+            if (e != hipSuccess) return e;
+            cus[dev] = prop.multiProcessorCount;
+            ready[dev] = true;
+        }
+        if (num_cus) *num_cus = cus[dev];
+        return hipSuccess;
+    }
+};
 
 // Thread-local error detail; returns `s` for convenient `return fail(...)`.
 bfx_status fail(bfx_status s, const char *fmt, ...);

@@ -250,38 +250,24 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
     }
 }
 
-int g_num_cus = 0;
+DeviceInit g_init;
 
-std::mutex g_mu;
-bool g_ready[64];
-
+// The twiddle table (per device) and the kernels' LDS attribute.
 hipError_t init_device() {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (g_ready[dev]) return hipSuccess;
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, dev);
-    if (e != hipSuccess) return e;
-    g_num_cus = prop.multiProcessorCount;
     static float2 host[kN];
     const double two_pi = 6.283185307179586476925286766559;
     for (int m = 0; m < kN; ++m) {
         host[m].x = (float)cos(two_pi * m / kN);
         host[m].y = (float)-sin(two_pi * m / kN);
     }
-    e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host, sizeof host, 0, hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host, sizeof host, 0, hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)fengine_kernel<true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)fengine_kernel<false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (e != hipSuccess) return e;
-    g_ready[dev] = true;
-    return hipSuccess;
+    return e;
 }
 
 }  // namespace
@@ -291,14 +277,15 @@ bool fengine_supported(int32_t ninput, int32_t nfft) { return nfft == kN && ninp
 hipError_t launch_fengine(const int8_t *in, int32_t ninput, int32_t nfft, int64_t nspec,
                           const float *scale, void *out, bool ci8, hipStream_t s) {
     if (!fengine_supported(ninput, nfft)) return hipErrorNotSupported;
-    hipError_t e = init_device();
+    int num_cus = 0;
+    const hipError_t e = g_init.ensure(init_device, &num_cus);
     if (e != hipSuccess) return e;
     const int ngroup = ninput / kGroup;
     const int64_t nspec8 = (nspec + 7) / 8 * 8;
     const int64_t total = nspec8 * ngroup;
     if (total > INT32_MAX) return hipErrorInvalidValue;
     // persistent grid: two workgroups per CU, a multiple of 8 (the XCD count)
-    int64_t grid = (int64_t)(g_num_cus > 0 ? g_num_cus : 256) * 2 / 8 * 8;
+    int64_t grid = (int64_t)num_cus * 2 / 8 * 8;
     if (grid < 8) grid = 8;
     if (grid > total) grid = total;
     if (ci8)

@@ -207,23 +207,15 @@ __global__ __launch_bounds__(F16Consumer::kThreads, 1) void xengine_f16_kernel(S
 typedef void (*F16Kernel)(SingleArray, int, int, int);
 const F16Kernel kF16[kXengineVariants] = {xengine_f16_kernel<4>, xengine_f16_kernel<8>};
 
-int g_num_cus = 0;
-std::once_flag g_init_once;
-hipError_t g_init_err = hipSuccess;
+DeviceInit g_init;
 
-void init_once() {
-    int dev = 0;
-    g_init_err = hipGetDevice(&dev);
-    if (g_init_err != hipSuccess) return;
-    hipDeviceProp_t prop;
-    g_init_err = hipGetDeviceProperties(&prop, dev);
-    if (g_init_err != hipSuccess) return;
-    g_num_cus = prop.multiProcessorCount;
+hipError_t set_attributes() {
     for (int v = 0; v < kXengineVariants; ++v) {
-        g_init_err = hipFuncSetAttribute((const void *)kF16[v], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         kLdsBytes);
-        if (g_init_err != hipSuccess) return;
+        const hipError_t e = hipFuncSetAttribute((const void *)kF16[v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kLdsBytes);
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -231,8 +223,9 @@ void init_once() {
 hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               float *out, bool overwrite, int variant, hipStream_t s) {
     if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
-    std::call_once(g_init_once, init_once);
-    if (g_init_err != hipSuccess) return g_init_err;
+    int num_cus = 0;
+    const hipError_t e = g_init.ensure(set_attributes, &num_cus);
+    if (e != hipSuccess) return e;
     SingleArray w;
     w.in = (const uint8_t *)in;
     w.out = out;
@@ -246,7 +239,7 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     w.npk = w.nb == 1 ? 4 : 1;
     w.ngroups = (nchan + w.npk - 1) / w.npk;
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
-    const int64_t grid = persistent_grid(g_num_cus, total_flat);
+    const int64_t grid = persistent_grid(num_cus, total_flat);
     hipLaunchKernelGGL(kF16[variant], dim3((unsigned)grid), dim3(F16Consumer::kThreads), kLdsBytes, s, w,
                        (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();

@@ -409,27 +409,19 @@ const BatchKernel kBatched[2][kXengineVariants] = {
     {xengine_batched_kernel<false, 4>, xengine_batched_kernel<false, 8>},
     {xengine_batched_kernel<true, 4>, xengine_batched_kernel<true, 8>}};
 
-int g_num_cus = 0;
-std::once_flag g_init_once;
-hipError_t g_init_err = hipSuccess;
+DeviceInit g_init;
 
-void init_once() {
-    int dev = 0;
-    g_init_err = hipGetDevice(&dev);
-    if (g_init_err != hipSuccess) return;
-    hipDeviceProp_t prop;
-    g_init_err = hipGetDeviceProperties(&prop, dev);
-    if (g_init_err != hipSuccess) return;
-    g_num_cus = prop.multiProcessorCount;
+hipError_t set_attributes() {
     for (int c = 0; c < 2; ++c)
         for (int v = 0; v < kXengineVariants; ++v) {
-            g_init_err = hipFuncSetAttribute((const void *)kSingle[c][v],
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-            if (g_init_err != hipSuccess) return;
-            g_init_err = hipFuncSetAttribute((const void *)kBatched[c][v],
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-            if (g_init_err != hipSuccess) return;
+            hipError_t e = hipFuncSetAttribute((const void *)kSingle[c][v],
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            if (e != hipSuccess) return e;
+            e = hipFuncSetAttribute((const void *)kBatched[c][v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBytes);
+            if (e != hipSuccess) return e;
         }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -442,8 +434,9 @@ int64_t xengine_items(int32_t ninput, int32_t nchan) {
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               int32_t *out, bool overwrite, int variant, hipStream_t s) {
     if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
-    std::call_once(g_init_once, init_once);
-    if (g_init_err != hipSuccess) return g_init_err;
+    int num_cus = 0;
+    const hipError_t e = g_init.ensure(set_attributes, &num_cus);
+    if (e != hipSuccess) return e;
     SingleArray w;
     w.in = (const uint8_t *)in;
     w.out = out;
@@ -457,7 +450,7 @@ hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t ncha
     w.npk = w.nb == 1 ? 4 : 1;
     w.ngroups = (nchan + w.npk - 1) / w.npk;
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
-    const int64_t grid = persistent_grid(g_num_cus, total_flat);
+    const int64_t grid = persistent_grid(num_cus, total_flat);
     hipLaunchKernelGGL(kSingle[ci4][variant], dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
                        kLdsBytes, s, w, (int)nt, (int)total_flat, (int)overwrite);
     return hipGetLastError();
@@ -467,8 +460,9 @@ hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, in
                                   int64_t nt, const BatchUnit *d_units, const int2 *d_work,
                                   int64_t nwork, void *out, bool overwrite, int variant, hipStream_t s) {
     if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
-    std::call_once(g_init_once, init_once);
-    if (g_init_err != hipSuccess) return g_init_err;
+    int num_cus = 0;
+    const hipError_t e = g_init.ensure(set_attributes, &num_cus);
+    if (e != hipSuccess) return e;
     BatchArray w;
     w.arena = (const uint8_t *)arena;
     w.out = (uint8_t *)out;
@@ -477,7 +471,7 @@ hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, in
     w.ntime = ntime;
     w.t0 = t0;
     w.bps = ci4 ? 1 : 2;
-    const int64_t grid = persistent_grid(g_num_cus, nwork);
+    const int64_t grid = persistent_grid(num_cus, nwork);
     hipLaunchKernelGGL(kBatched[ci4][variant], dim3((unsigned)grid), dim3(IntKernelConsumer<true>::kThreads),
                        kLdsBytes, s, w, (int)nt, (int)nwork, (int)overwrite);
     return hipGetLastError();
