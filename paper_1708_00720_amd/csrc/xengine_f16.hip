@@ -21,10 +21,11 @@
 //
 // Epilogue.  In the 32x32 MFMA output layout (lane l, register v hold real row
 // 8*(v/4) + 4*(l/32) + v%4, real column l%32) the four real products of a
-// complex pair sit in two adjacent registers of two adjacent lanes.  One DPP
-// lane swap per register pair brings them together: even lanes finish the
-// even complex row of each register quad, odd lanes the odd one, so every
-// lane stores.
+// complex pair sit in two adjacent registers of two adjacent lanes.  Each
+// lane swaps the four registers of a quad with its neighbour (DPP) and forms
+// both rows' results from its own and the neighbour's values: even lanes keep
+// the even complex row of the quad, odd lanes the odd one, so every lane
+// stores.
 //
 // Accuracy.  binary16 x binary16 products are exact in binary32; the error is
 // the binary32 summation over T samples: |dV_ij| <= ~T u sum_t |x_i||x_j|
