@@ -237,6 +237,12 @@ __device__ __forceinline__ void stage_tail(const StagePre &pre, const StageRaw<C
 // loaded, then added, then stored: no store waits on a load issued after an
 // earlier store (a wait for one load's data also waits for every store
 // before it).
+// Four int32 at an 8-byte-aligned address (one 16-byte store).
+typedef int v4i8a __attribute__((ext_vector_type(4), aligned(8)));
+
+// Swap with the neighbouring lane (DPP quad_perm [1,0,3,2]).
+__device__ __forceinline__ int swap_lane(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
+
 template <bool CI4>
 __device__ __forceinline__ void store_sub(uint8_t *obase, int irow0, int jcol0, const v16i &re, const v16i &pp,
                                           const v16i &qq, int lane, int ninput, int overwrite) {
@@ -277,8 +283,21 @@ __device__ __forceinline__ void store_sub(uint8_t *obase, int irow0, int jcol0, 
         __builtin_amdgcn_sched_barrier(0);
     }
     if (interior) {
+        // Neighbouring lanes hold neighbouring columns of the same rows.  Each
+        // lane pair swaps registers v and v+1 (rows d and d+1) with DPP, so the
+        // even lane stores columns (jj, jj+1) of row d and the odd lane columns
+        // (jj-1, jj) of row d+1: 16 bytes each, half the store instructions.
+        // Every select below has one swapped operand, so none becomes a
+        // per-lane indexed read of the accumulators.
+        const bool odd = lane & 1;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) *dst(v) = res[v];
+        for (int v = 0; v < 16; v += 2) {
+            const int2 a = res[v], b = res[v + 1];
+            const int sax = swap_lane(a.x), say = swap_lane(a.y);
+            const int sbx = swap_lane(b.x), sby = swap_lane(b.y);
+            const v4i8a out = odd ? v4i8a{sbx, sby, b.x, b.y} : v4i8a{a.x, a.y, sax, say};
+            *(v4i8a *)(odd ? (uint8_t *)dst(v + 1) - 8 : (uint8_t *)dst(v)) = out;
+        }
     } else {
 #pragma unroll
         for (int v = 0; v < 16; ++v)
