@@ -25,9 +25,10 @@
 // swizzled by the row index so the 16 rows of a B fragment read hit distinct
 // banks.
 //
-// Tiles.  Work unit = (channel, 128 samples, 32 beams); wave w owns beams
-// 8w..8w+7 (16 real MFMA rows) for all 128 samples (8 tiles of 16 samples,
-// 8 x 4 FP32 accumulators per lane).  Its W' fragments for the whole K chunk
+// Tiles.  Work unit = (channel, 256 samples, 32 beams); wave w owns beams
+// 8w..8w+7 (16 real MFMA rows) for all 256 samples (16 tiles of 16 samples,
+// 16 x 4 FP32 accumulators per lane: the longer the unit, the fewer times a
+// chunk's weights and its first stages are waited for).  Its W' fragments for the whole K chunk
 // (16 K steps x 8 binary16 per lane) are expanded from the cf16 weights into
 // registers once per chunk; the K loop then runs on LDS reads and MFMAs only.
 // Two workgroups share a CU.
@@ -57,7 +58,7 @@ constexpr int kBeams = 32;      // beams per unit: 4 waves x 8 beams
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kS = 16;          // samples per stage (one MFMA column tile)
-constexpr int kNT = 8;          // stages per unit and K chunk
+constexpr int kNT = 16;         // stages per unit and K chunk
 constexpr int kTB = kS * kNT;   // samples per unit
 constexpr int kKC = 256;        // complex inputs per K chunk
 constexpr int kKS = kKC / 16;   // MFMA K steps (32 real K = 16 inputs) per chunk
