@@ -184,3 +184,25 @@ def test_fp16_items_span_several_rounds(T):
     banner(f"xengine cf16 multi-round T={T} F={F} N={N}")
     x = synth.cf16_voltages(80 + T, T, F, N)
     _check(_host(_run(x, T, F, N), F, N), _oracle(x), N, T, f"cf16 multi-round T={T}")
+
+
+def test_dump_full_size_running_sum():
+    """The dump at the FP16 workload's size (2048 channels x 131,328
+    baselines, 537 M binary32 values, one thread per four values): the copy is
+    exact and two dumps add exactly 2 * value in binary64 everywhere."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    F, N = 2048, 512
+    banner(f"dump full size F={F} N={N}")
+    plan = bfx.bfx_xengine_create(N, F, "cf16")
+    acc = bfx.visibilities_buffer(plan)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    acc.copy_(torch.randn(acc.numel(), device="cuda", generator=g).view(acc.shape))
+    out = torch.zeros_like(acc)
+    run64 = torch.zeros(acc.numel(), dtype=torch.float64, device="cuda")
+    bfx.bfx_xengine_dump(plan, acc, out, run64)
+    bfx.bfx_xengine_dump(plan, acc, None, run64)
+    torch.cuda.synchronize()
+    assert torch.equal(out, acc)
+    assert torch.equal(run64, 2.0 * acc.reshape(-1).double())
+    plan.close()
