@@ -81,8 +81,9 @@ def test_beamform_navg(navg):
     (32, 1, 1, 16, 16),      # smallest unit: one beam, one window
     (96, 3, 8, 64, 4),       # one partial K chunk of 24 16-byte chunks per row (not 16k)
     (544, 2, 40, 48, 16),    # three K chunks (256 + 256 + 32 inputs), two beam groups, ragged time
-    (1056, 1, 70, 272, 8),   # five K chunks, three beam groups, two time blocks + tail
+    (1056, 1, 70, 272, 8),   # five K chunks, three beam groups, a 256-sample unit + a 16-sample tail
     (512, 9, 32, 512, 16),   # channel count not a multiple of 8
+    (256, 2, 16, 600, 8),    # two full 256-sample units + an 88-sample tail
 ])
 def test_beamform_ragged(N, F, B, T, navg):
     banner(f"beamform ragged N={N} F={F} B={B} T={T} navg={navg}")
