@@ -244,16 +244,18 @@ int orc_dft_real(const int8_t *x, int32_t ninput, int32_t nfft, int64_t nspec,
 /* ------------------------------------------------------------------------ */
 /* Requantize to 8+8.  Reading: a caller-supplied per-channel scale, round half
  * to even, saturate to the symmetric range [-127, 127] (so -128 is never
- * produced).  The rounding decision is taken in single precision, as the
- * kernel takes it: q = sat(rint_even(fl32(scale * fl32(v)))).
+ * produced).  The paper's quantize module (Sec. 2.2) fixes no rounding rule;
+ * the definition taken is the exact one, q = sat(rint_even(scale * v)) on the
+ * double spectrum value v and the binary32 scale widened to double.  A binary32
+ * implementation can round the other way only where scale * v lies within its
+ * own error of a half-integer.
  * X is [nspec][nchan][ninput][2] double, out is [nspec][nchan][ninput][2] int8. */
 static int8_t requant_one(double v, float scale)
 {
-    float prod = scale * (float)v;
-    float r = rintf(prod); /* default rounding mode: half to even */
-    if (r > 127.0f) r = 127.0f;
-    if (r < -127.0f) r = -127.0f;
-    if (r != r) r = 0.0f; /* NaN never arises from finite input */
+    double r = rint((double)scale * v); /* default rounding mode: half to even */
+    if (r > 127.0) r = 127.0;
+    if (r < -127.0) r = -127.0;
+    if (r != r) r = 0.0; /* NaN never arises from finite input */
     return (int8_t)r;
 }
 

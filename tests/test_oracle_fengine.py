@@ -121,11 +121,14 @@ def test_requantize_applies_scale():
     assert re == [2, 5, -4]  # 1.5 -> 2, 5 -> 5, -3.5 -> -4
 
 
-def test_requantize_decision_in_single_precision():
-    # 0.5 + 1e-12 is above the tie in double but equal to it in binary32;
-    # the decision follows binary32 (the kernel's precision): round to 0.
-    re, _ = _rq([0.5 + 1e-12, 1.5 - 1e-12])
-    assert re == [0, 2]
+def test_requantize_decision_on_the_exact_product():
+    # 0.5 + 1e-12 lies above the tie and 1.5 - 1e-12 below it; binary32 would
+    # see both as exact ties.  The definition rounds the exact product.
+    re, _ = _rq([0.5 + 1e-12, 1.5 - 1e-12, -0.5 - 1e-12])
+    assert re == [1, 1, -1]
+    # the scale is the binary32 value widened exactly: 0.1f * 5 = 0.50000000745
+    re, _ = _rq([5.0], scale=0.1)
+    assert re == [1]
 
 
 def test_requantize_per_channel_scale():
