@@ -50,9 +50,10 @@ def _load():
         _lib.orc_dft_real.argtypes = [vp, i32, i32, i64, vp, ci]
         _lib.orc_requantize.argtypes = [vp, vp, i64, i32, i32, vp]
         _lib.orc_beamform_detect.argtypes = [vp, vp, vp, vp, i64, i32, i32, i32, i32, vp, ci]
+        _lib.orc_beamform_ci4.argtypes = [vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, ci]
         for name in ("orc_unpack_ci4", "orc_unpack_ci8", "orc_xengine_int", "orc_xengine_f64",
                      "orc_accumulate_f64", "orc_dft_real", "orc_requantize",
-                     "orc_beamform_detect", "orc_max_threads"):
+                     "orc_beamform_detect", "orc_beamform_ci4", "orc_max_threads"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -171,3 +172,21 @@ def beamform_detect(xre, xim, wre, wim, navg: int, nthreads: int = 0):
     _check(_load().orc_beamform_detect(_ptr(xr), _ptr(xi), _ptr(wr), _ptr(wi), nt, nf, n, nb,
                                        navg, _ptr(out), nthreads), "beamform_detect")
     return out
+
+
+def beamform_ci4(x: np.ndarray, w: np.ndarray, scale: np.ndarray, navg: int, want_y: bool = False,
+                 nthreads: int = 0):
+    """Integer beamformer on ci4 voltages x (uint8 [T][F][N]) with int8 weights
+    w ([F][B][N][2]) and per-beam binary32 scales: returns the binary32 beam
+    power [B][F][T/navg] (and the exact int64 beams [B][F][T][2] if want_y)."""
+    xa = np.ascontiguousarray(x, np.uint8)
+    wa = np.ascontiguousarray(w, np.int8)
+    sa = np.ascontiguousarray(scale, np.float32)
+    nt, nf, n = xa.shape
+    nf2, nb, n2, two = wa.shape
+    assert nf2 == nf and n2 == n and two == 2 and sa.shape == (nb,)
+    power = np.zeros((nb, nf, nt // navg), np.float32)
+    y = np.zeros((nb, nf, nt, 2), np.int64) if want_y else None
+    _check(_load().orc_beamform_ci4(_ptr(xa), _ptr(wa), _ptr(sa), nt, nf, n, nb, navg, _ptr(power),
+                                    _ptr(y) if want_y else None, nthreads), "beamform_ci4")
+    return (power, y) if want_y else power

@@ -311,3 +311,62 @@ int orc_beamform_detect(const double *xre, const double *xim, const double *wre,
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Phase-and-sum beamformer on 4+4-bit voltages with 8-bit integer weights
+ * (paper Sec. 6, DRX pipeline: the GPU beamformer takes the 4+4 complex
+ * samples directly, without unpacking them first), square-law detection and
+ * integration (Sec. 4.1 detect and accumulate blocks).
+ *
+ *   y[b][f][t] = sum_i w[f][b][i] * x[t][f][i]         (complex, no conjugation,
+ *                                                       exact in int64)
+ *   S[b][f][u] = sum_{t = u*navg}^{u*navg+navg-1} |y[b][f][t]|^2   (int64)
+ *   P[b][f][u] = fl32( fl64( fl64(scale_b * scale_b) * fl64(S) ) )
+ *
+ * Reading: the weights are integers w_int with a per-beam binary32 scale
+ * scale_b (physical weight scale_b * w_int), so the physical power is
+ * scale_b^2 * S.  The binary32 result is defined by the rounding steps above:
+ * scale_b^2 is exact in double; S is converted to double (exact below 2^53),
+ * the product rounded to double, then to binary32.
+ *
+ * x: ci4 bytes [ntime][nchan][ninput]; w: int8 [nchan][nbeam][ninput][2]
+ * (re, im); scale: float[nbeam]; power: float [nbeam][nchan][ntime/navg];
+ * y (optional, may be NULL): int64 [nbeam][nchan][ntime][2].               */
+int orc_beamform_ci4(const uint8_t *x, const int8_t *w, const float *scale, int64_t ntime,
+                     int32_t nchan, int32_t ninput, int32_t nbeam, int32_t navg,
+                     float *power, int64_t *y, int nthreads)
+{
+    if (!x || !w || !scale || !power) return ORC_EINVAL;
+    if (ntime < 0 || nchan <= 0 || ninput <= 0 || nbeam <= 0 || navg <= 0) return ORC_EINVAL;
+    if (ntime % navg) return ORC_EINVAL;
+    const int64_t nout = ntime / navg;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int32_t f = 0; f < nchan; ++f) {
+        for (int32_t b = 0; b < nbeam; ++b) {
+            for (int64_t u = 0; u < nout; ++u) {
+                int64_t s = 0;
+                for (int64_t t = u * navg; t < (u + 1) * navg; ++t) {
+                    int64_t yr = 0, yi = 0;
+                    for (int32_t i = 0; i < ninput; ++i) {
+                        int64_t wx = (((int64_t)f * nbeam + b) * ninput + i) * 2;
+                        int64_t wr = w[wx], wi = w[wx + 1];
+                        int byte = x[(t * nchan + f) * (int64_t)ninput + i];
+                        int64_t xr = nibble_value(byte >> 4), xi = nibble_value(byte);
+                        yr += wr * xr - wi * xi;
+                        yi += wr * xi + wi * xr;
+                    }
+                    if (y) {
+                        int64_t o = (((int64_t)b * nchan + f) * ntime + t) * 2;
+                        y[o] = yr;
+                        y[o + 1] = yi;
+                    }
+                    s += yr * yr + yi * yi;
+                }
+                double sb2 = (double)scale[b] * (double)scale[b];
+                power[((int64_t)b * nchan + f) * nout + u] = (float)(sb2 * (double)s);
+            }
+        }
+    }
+    return ORC_OK;
+}
