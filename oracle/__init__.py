@@ -51,9 +51,11 @@ def _load():
         _lib.orc_requantize.argtypes = [vp, vp, i64, i32, i32, vp]
         _lib.orc_beamform_detect.argtypes = [vp, vp, vp, vp, i64, i32, i32, i32, i32, vp, ci]
         _lib.orc_beamform_ci4.argtypes = [vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, ci]
+        _lib.orc_tengine.argtypes = [vp, i32, i32, i64, i32, i32, i64, i64, ctypes.c_float, ci, vp, vp,
+                                     ci]
         for name in ("orc_unpack_ci4", "orc_unpack_ci8", "orc_xengine_int", "orc_xengine_f64",
                      "orc_accumulate_f64", "orc_dft_real", "orc_requantize",
-                     "orc_beamform_detect", "orc_beamform_ci4", "orc_max_threads"):
+                     "orc_beamform_detect", "orc_beamform_ci4", "orc_tengine", "orc_max_threads"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -190,3 +192,20 @@ def beamform_ci4(x: np.ndarray, w: np.ndarray, scale: np.ndarray, navg: int, wan
     _check(_load().orc_beamform_ci4(_ptr(xa), _ptr(wa), _ptr(sa), nt, nf, n, nb, navg, _ptr(power),
                                     _ptr(y) if want_y else None, nthreads), "beamform_ci4")
     return (power, y) if want_y else power
+
+
+def tengine(x: np.ndarray, chan0: int, nfft: int, mix_num: int, mix_den: int, scale: float,
+            out_bits: int = 8, want_z: bool = False, nthreads: int = 0):
+    """T-engine of ci8 spectra x (int8 [S][F][N][2]): channels chan0..chan0+nfft-1
+    shifted, inverse transformed (1/nfft), mixed by exp(2 pi i (mix_num t mod
+    mix_den)/mix_den) and quantized to +-127 (out_bits 8) or +-7 (out_bits 4).
+    Returns int32 codes [S*nfft][N][2] (and the double z' if want_z)."""
+    a = np.ascontiguousarray(x, np.int8)
+    nspec, nchan, ninput, two = a.shape
+    assert two == 2
+    q = np.zeros((nspec * nfft, ninput, 2), np.int32)
+    z = np.zeros((nspec * nfft, ninput, 2), np.float64) if want_z else None
+    _check(_load().orc_tengine(_ptr(a), nchan, ninput, nspec, chan0, nfft, mix_num, mix_den,
+                               float(scale), out_bits, _ptr(q), _ptr(z) if want_z else None,
+                               nthreads), "tengine")
+    return (q, z) if want_z else q

@@ -370,3 +370,79 @@ int orc_beamform_ci4(const uint8_t *x, const int8_t *w, const float *scale, int6
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* T-engine: channelized spectra back to a time series (paper Sec. 6, TBN
+ * pipeline and DRX T-engine): complex samples are converted to floating
+ * point, reduced in bandwidth to nfft channels starting at chan0, shifted
+ * along the channel axis so the centre of the kept band sits at zero
+ * frequency, inverse transformed, multiplied by a complex mixer for
+ * sub-channel tuning, and quantized to 8+8 or 4+4 bit complex integers.
+ *
+ *   X_k   = x[s][chan0 + k][i],  k = 0 .. nfft-1          (ci8 input)
+ *   z[n]  = (1/nfft) sum_k X_k exp(+2 pi i (k - nfft/2) n / nfft)
+ *   z'[n] = z[n] exp(+2 pi i ((mix_num * t) mod mix_den) / mix_den),
+ *           t = s * nfft + n (the mixer phase runs on across frames)
+ *   q     = clamp(rint_half_even(scale * z'), -L, L) per component,
+ *           L = 127 (out_bits 8) or 7 (out_bits 4).
+ *
+ * Readings (the paper names the steps, not their conventions): the inverse
+ * transform is normalised by 1/nfft (the convention of the library inverse FFT
+ * the paper's TBN pipeline calls); the shift maps channel chan0 + nfft/2 to
+ * zero frequency; the mixer frequency is the exact fraction mix_num/mix_den
+ * cycles per output sample; quantization is symmetric (4+4 never uses -8).
+ * Phases are reduced exactly in integers before cos/sin in double.
+ * Output: int32 [nspec * nfft][ninput][2] codes (the caller packs them).    */
+int orc_tengine(const int8_t *x, int32_t nchan, int32_t ninput, int64_t nspec, int32_t chan0,
+                int32_t nfft, int64_t mix_num, int64_t mix_den, float scale, int out_bits,
+                int32_t *q, double *z_out, int nthreads)
+{
+    if (!x || !q || nchan <= 0 || ninput <= 0 || nspec < 0 || nfft <= 0 || (nfft & 1)) return ORC_EINVAL;
+    if (chan0 < 0 || chan0 + nfft > nchan || mix_den <= 0 || mix_num < 0) return ORC_EINVAL;
+    if (out_bits != 8 && out_bits != 4) return ORC_EINVAL;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double lim = out_bits == 8 ? 127.0 : 7.0;
+    double *c = (double *)malloc(sizeof(double) * nfft);
+    double *sn = (double *)malloc(sizeof(double) * nfft);
+    if (!c || !sn) { free(c); free(sn); return ORC_EINVAL; }
+    for (int32_t m = 0; m < nfft; ++m) {
+        c[m] = cos(two_pi * m / nfft);
+        sn[m] = sin(two_pi * m / nfft);
+    }
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t sp = 0; sp < nspec; ++sp) {
+        for (int32_t i = 0; i < ninput; ++i) {
+            for (int32_t n = 0; n < nfft; ++n) {
+                double zr = 0.0, zi = 0.0;
+                for (int32_t k = 0; k < nfft; ++k) {
+                    int64_t ix = ((sp * nchan + chan0 + k) * (int64_t)ninput + i) * 2;
+                    double xr = x[ix], xi = x[ix + 1];
+                    /* phase index (k - nfft/2) n mod nfft, non-negative */
+                    int64_t m = (((int64_t)(k - nfft / 2) * n) % nfft + nfft) % nfft;
+                    zr += xr * c[m] - xi * sn[m];
+                    zi += xr * sn[m] + xi * c[m];
+                }
+                zr /= nfft;
+                zi /= nfft;
+                int64_t t = sp * nfft + n;
+                int64_t pm = (int64_t)(((unsigned __int128)mix_num * (unsigned __int128)t) % (unsigned __int128)mix_den);
+                double ph = two_pi * (double)pm / (double)mix_den;
+                double cr = cos(ph), ci = sin(ph);
+                double ur = zr * cr - zi * ci, ui = zr * ci + zi * cr;
+                int64_t o = (t * ninput + i) * 2;
+                if (z_out) { z_out[o] = ur; z_out[o + 1] = ui; }
+                double a = rint((double)scale * ur), b = rint((double)scale * ui);
+                if (a > lim) a = lim;
+                if (a < -lim) a = -lim;
+                if (b > lim) b = lim;
+                if (b < -lim) b = -lim;
+                q[o] = (int32_t)a;
+                q[o + 1] = (int32_t)b;
+            }
+        }
+    }
+    free(c);
+    free(sn);
+    return ORC_OK;
+}
