@@ -4,14 +4,17 @@
 Workload (the streaming configuration the headline metric is quoted on):
 352 antennas x 2 polarisations = 704 inputs, 192 channels, ci4 voltages
 (rounded Gaussian sigma=2.5 clipped to +-7), 1000 samples per integration.
-A step streams 100 gulps through a 4-slot device ring (the paper's default
-ring = 4 gulps): each gulp is one integration, correlated with
-BFX_ACC_OVERWRITE into the visibility buffer and handed over by dump.  All
+A step streams 100 gulps through a 4-slot device ring of input gulps (the
+paper's default ring = 4 gulps): gulp g is one integration, correlated with
+BFX_ACC_OVERWRITE into slot g % 4 of a 4-slot ring of visibility buffers and
+handed over there by dump (no copy: the consumer reads the slot).  All
 inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  Extra fields: input GB/s, the dominant kernel's
-roofline (HIP-event-timed launches on the launch stream) and the CPU oracle's
-rate on a bounded sample.
+roofline (HIP-event-timed launches on the launch stream), graph-replay
+timing of one ring cycle (median, p10, p90), the CPU oracle's rate on a
+bounded sample, and the parity of the benchmarked ring's visibilities with
+the oracle on the channels the CPU sample computed.
 """
 import argparse
 import hashlib
@@ -55,24 +58,47 @@ def measured_traffic(per_launch_cmac):
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(raw_gulp, budget_s=15.0):
-    """Oracle X-engine on whole channels of one gulp until ~budget_s elapses."""
+    """Oracle X-engine on whole channels of one gulp until ~budget_s elapses
+    (all OpenMP threads), plus one channel on a single thread.  Returns the
+    record and the oracle's visibilities of the channels it computed."""
+    import numpy as np
     import oracle
     threads = oracle.max_threads()
     done_ch = 0
     t0 = time.perf_counter()
     f = 0
+    parts = []
     while time.perf_counter() - t0 < budget_s and done_ch < N_CHAN:
         nf = min(threads, N_CHAN - f)
-        oracle.xengine_int(raw_gulp, "ci4", N_TIME, N_CHAN, N_INPUT, chans=(f, nf),
-                           nthreads=threads)
+        parts.append(oracle.xengine_int(raw_gulp, "ci4", N_TIME, N_CHAN, N_INPUT, chans=(f, nf),
+                                        nthreads=threads))
         f += nf
         done_ch += nf
     dt = time.perf_counter() - t0
-    cmac = done_ch * N_TIME * N_INPUT * (N_INPUT + 1) // 2
-    return {"value": cmac / dt / 1e12, "unit": "TeraCMAC/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done_ch} of {N_CHAN} channels of one 704-input ci4 gulp "
-                      f"({N_TIME} samples), int64 triple loop, {dt:.1f} s"}
+    cmac_ch = N_TIME * N_INPUT * (N_INPUT + 1) // 2
+    t1 = time.perf_counter()
+    oracle.xengine_int(raw_gulp, "ci4", N_TIME, N_CHAN, N_INPUT, chans=(N_CHAN - 1, 1), nthreads=1)
+    dt1 = time.perf_counter() - t1
+    rec = {"value": done_ch * cmac_ch / dt / 1e12, "unit": "TeraCMAC/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{done_ch} of {N_CHAN} channels of one 704-input ci4 gulp "
+                     f"({N_TIME} samples), int64 triple loop, {dt:.1f} s",
+           "single_thread_value": cmac_ch / dt1 / 1e12,
+           "single_thread_sample": f"channel {N_CHAN - 1} of the same gulp on one thread, {dt1:.1f} s",
+           "cpu_model": cpu_model()}
+    return rec, np.concatenate(parts, axis=0)
 
 
 PEAK_FP16_TFLOPS = 2500.0  # MI355X dense FP16 MFMA
@@ -99,6 +125,66 @@ def time_launches(fn, reps, warm=2):
     torch.cuda.synchronize()
     d = sorted(a.elapsed_time(b) for a, b in evs)
     return sum(d) / len(d), d[len(d) // 2], d[0]
+
+
+def measured_peaks():
+    """Sustainable rates of this device from the library's peak probes: dense
+    MFMA (int8 and binary16, back-to-back MFMAs on 8 independent accumulators
+    per wave, no memory traffic) and HBM reads (a 2 GiB buffer streamed once
+    with 16-byte loads).  Best of 5 event-timed launches each."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, kind in (("int8_mfma_TOPs", bfx.BFX_PROBE_MFMA_I8), ("fp16_mfma_TFLOPs", bfx.BFX_PROBE_MFMA_F16)):
+        iters, nb = 2000, 4 * ncu
+        _, _, best = time_launches(lambda: bfx.bfx_probe_mfma(kind, iters, nb, sink), 5)
+        out[name] = round(bfx.bfx_probe_mfma_ops(kind, iters, nb) / (best * 1e-3) / 1e12, 1)
+    buf = torch.ones(1 << 29, dtype=torch.int32, device="cuda")  # 2 GiB
+    nbytes = buf.numel() * 4
+    _, _, best = time_launches(lambda: bfx.bfx_probe_read(buf, nbytes, 32 * ncu, sink), 5)
+    out["hbm_read_GBps"] = round(nbytes / (best * 1e-3) / 1e9, 1)
+    out["int8_frac_of_published"] = round(out["int8_mfma_TOPs"] / PEAK_INT8_TOPS, 3)
+    out["fp16_frac_of_published"] = round(out["fp16_mfma_TFLOPs"] / PEAK_FP16_TFLOPS, 3)
+    out["hbm_frac_of_published"] = round(out["hbm_read_GBps"] / PEAK_HBM_GBPS, 3)
+    out["compute_units"] = ncu
+    del buf
+    return out
+
+
+def graph_replay_timing(gulp, replays, warm=5):
+    """One ring cycle (4 gulps: accumulate with overwrite + dump each)
+    captured in a HIP graph, replayed `replays` times after `warm` warm-up
+    replays, each replay bracketed by HIP events on the replay stream.
+    Returns per-gulp median, p10 and p90 (microseconds)."""
+    import numpy as np
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for k in range(N_SLOT):
+            gulp(k, s.cuda_stream)
+    torch.cuda.synchronize()
+    for _ in range(warm):
+        g.replay()
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(replays)]
+    for a, b in evs:
+        a.record(cur)
+        g.replay()
+        b.record(cur)
+    torch.cuda.synchronize()
+    per_gulp = np.array([a.elapsed_time(b) for a, b in evs]) * 1e3 / N_SLOT
+    med = float(np.median(per_gulp))
+    return {"replays": replays, "gulps_per_replay": N_SLOT,
+            "us_per_gulp_median": round(med, 2),
+            "us_per_gulp_p10": round(float(np.percentile(per_gulp, 10)), 2),
+            "us_per_gulp_p90": round(float(np.percentile(per_gulp, 90)), 2),
+            "tcmac_per_s_median": round(cmac_per_gulp() / (med * 1e-6) / 1e12, 2)}
 
 
 def _row(kernel, workload, avg_ms, med_ms, work, work_unit, peak, peak_unit, bound, nbytes,
@@ -207,6 +293,35 @@ def row_beamform(reps, x=None):
     return r
 
 
+def row_beamform_ci4(reps):
+    """Integer beamformer on ci4: 512 inputs, 2048 channels, 1024 samples,
+    32 beams of int8 quantized unit-modulus weights, navg 16."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    T, F, N, B, NAVG = 1024, 2048, 512, 32, 16
+    g = torch.Generator(device="cuda").manual_seed(9)
+    z = torch.randn(2, T * F * N, device="cuda", generator=g)
+    re = torch.clamp(torch.round(2.5 * z[0]), -7, 7).to(torch.int32)
+    im = torch.clamp(torch.round(2.5 * z[1]), -7, 7).to(torch.int32)
+    x = (((re & 15) << 4) | (im & 15)).to(torch.uint8)
+    del z, re, im
+    th = torch.rand(F * B * N, device="cuda", dtype=torch.float64, generator=g) * (2 * torch.pi)
+    w = torch.stack([torch.round(127 * torch.cos(th)), torch.round(127 * torch.sin(th))],
+                    dim=-1).to(torch.int8).reshape(-1)
+    del th
+    scale = torch.full((B,), 1.0 / 127, dtype=torch.float32, device="cuda")
+    out = torch.empty(B * F * (T // NAVG), dtype=torch.float32, device="cuda")
+    avg, med, _ = time_launches(lambda: bfx.bfx_beamform_ci4(x, w, scale, N, F, B, T, NAVG, out), reps)
+    cmac = B * F * T * N
+    nbytes = T * F * N + F * B * N * 2 + out.numel() * 4
+    r = _row("beamform_ci4_kernel<4>", "512 inputs x 2048 channels x 1024 samples ci4, 32 int8 beams, navg 16",
+             avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
+             {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
+              "int8_mfma_frac": round(8 * cmac / (avg * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)})
+    del x, w, out
+    return r
+
+
 def row_batched(reps):
     """Batched: 8 subarrays (32..512 inputs, 1024..64 channels), ci8, 256
     samples, one persistent launch; also each subarray alone for comparison."""
@@ -266,8 +381,12 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the other hot-path rows (F-engine, FP16 X, beamformer, batched)")
+    ap.add_argument("--peak-probes", action="store_true",
+                    help="only run the library's MFMA and HBM peak probes")
     ap.add_argument("--row-reps", type=int, default=20)
-    ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "batched"],
+    ap.add_argument("--graph-replays", type=int, default=60,
+                    help="replays of the captured 4-gulp ring cycle (timed one by one)")
+    ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "beamform_ci4", "batched"],
                     help="only time one row (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -296,9 +415,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 1 << 30}), flush=True)
         return
+    if args.peak_probes:
+        print(json.dumps(measured_peaks()), flush=True)
+        return
     if args.only_row:
         fn = {"fengine": row_fengine, "xf16": lambda r: row_xengine_f16(r)[0],
-              "beamform": row_beamform, "batched": row_batched}[args.only_row]
+              "beamform": row_beamform, "beamform_ci4": row_beamform_ci4,
+              "batched": row_batched}[args.only_row]
         print(json.dumps(fn(args.row_reps)), flush=True)
         return
     if args.profile_launches:
@@ -330,22 +453,27 @@ def main():
     tune_us = bfx.bfx_xengine_autotune(plan, N_TIME)
     variant = bfx.bfx_xengine_variant(plan)
     print(f"[bench] autotune: variant {variant}, times {tune_us} us", file=sys.stderr, flush=True)
-    vis = bfx.visibilities_buffer(plan, device=dev)
+    # ring of visibility buffers: gulp g's integration lands in slot g % 4
+    vis = [bfx.visibilities_buffer(plan, device=dev) for _ in range(N_SLOT)]
     handle = plan.handle
     lib = bfx._lib
     s_ptr = stream.cuda_stream
-    acc_ptr = vis.data_ptr()
+    acc_ptrs = [v.data_ptr() for v in vis]
     slot_ptrs = [ring[k].data_ptr() for k in range(N_SLOT)]
+
+    def gulp(g, sp):
+        st = lib.bfx_xengine_accumulate(handle, slot_ptrs[g % N_SLOT], N_TIME, acc_ptrs[g % N_SLOT],
+                                        bfx.BFX_ACC_OVERWRITE, sp)
+        if st != 0:
+            raise bfx.BfxError(st, bfx.bfx_last_error_detail())
+        # hand-over in place: the consumer reads the slot (no copy, no running sum)
+        st = lib.bfx_xengine_dump(handle, acc_ptrs[g % N_SLOT], None, None, sp)
+        if st != 0:
+            raise bfx.BfxError(st, bfx.bfx_last_error_detail())
 
     def step():
         for g in range(N_GULP):
-            st = lib.bfx_xengine_accumulate(handle, slot_ptrs[g % N_SLOT], N_TIME, acc_ptr,
-                                            bfx.BFX_ACC_OVERWRITE, s_ptr)
-            if st != 0:
-                raise bfx.BfxError(st, bfx.bfx_last_error_detail())
-            st = lib.bfx_xengine_dump(handle, acc_ptr, acc_ptr, None, s_ptr)
-            if st != 0:
-                raise bfx.BfxError(st, bfx.bfx_last_error_detail())
+            gulp(g, s_ptr)
 
     for _ in range(args.warmup):
         step()
@@ -372,7 +500,7 @@ def main():
            for _ in range(reps)]
     for r in range(reps):
         evs[r][0].record(stream)
-        lib.bfx_xengine_accumulate(handle, slot_ptrs[r % N_SLOT], N_TIME, acc_ptr,
+        lib.bfx_xengine_accumulate(handle, slot_ptrs[r % N_SLOT], N_TIME, acc_ptrs[r % N_SLOT],
                                    bfx.BFX_ACC_OVERWRITE, s_ptr)
         evs[r][1].record(stream)
     torch.cuda.synchronize()
@@ -396,6 +524,11 @@ def main():
         "hbm_GBps_algorithmic": round((gulp_bytes + out_bytes) / (avg_ms * 1e-3) / 1e9, 1),
     }
 
+    graph = graph_replay_timing(gulp, args.graph_replays)
+    print("[bench] peak probes", file=sys.stderr, flush=True)
+    peaks = measured_peaks()
+    roofline["frac_of_measured_int8_peak"] = round(achieved / peaks["int8_mfma_TOPs"], 4)
+
     rows = None
     if not args.no_rows:
         rows = {}
@@ -406,14 +539,25 @@ def main():
         print("[bench] row: beamformer", file=sys.stderr, flush=True)
         rows["beamform"] = row_beamform(args.row_reps, x16)
         del x16
+        print("[bench] row: ci4 beamformer", file=sys.stderr, flush=True)
+        rows["beamform_ci4"] = row_beamform_ci4(args.row_reps)
         print("[bench] row: batched", file=sys.stderr, flush=True)
         rows["batched"] = row_batched(args.row_reps)
         torch.cuda.empty_cache()
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(first_gulp)
+        cpu, want = cpu_baseline(first_gulp)
+        # the benchmarked ring's slot 0 holds gulp 0's integration
+        P = N_INPUT * (N_INPUT + 1) // 2
+        nch = want.shape[0]
+        got = vis[0][:nch * P * 2].cpu().numpy().astype(np.int64).reshape(nch, P, 2)
+        parity = {"visibility_slot": 0, "channels_checked": int(nch),
+                  "bit_exact_vs_oracle": bool(np.array_equal(got, want))}
+        print(f"[bench] parity of ring slot 0 on {nch} channels: "
+              f"{parity['bit_exact_vs_oracle']}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC,
@@ -437,7 +581,10 @@ def main():
         },
         "input_GBps": round(in_gbs, 2),
         "roofline": roofline,
+        "graph_replay": graph,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
+        "parity": parity,
         "rows": rows,
     }
     print(json.dumps(line), flush=True)

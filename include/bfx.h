@@ -181,7 +181,13 @@ int32_t bfx_tune_cache_lookup(const char *path, const char *arch, const char *dt
  *          V, otherwise V is added to it.
  * Returns BFX_ERANGE, without enqueueing, when the integer bound
  * bfx_xengine_max_ntime would be exceeded by nacc + ntime.  Results do not
- * depend on launch shape or scheduling (integer sums are exact).            */
+ * depend on launch shape or scheduling (integer sums are exact).
+ * Graph capture: the bound is checked when a call is captured, and every
+ * replay of the graph repeats the captured launches.  A call without
+ * BFX_ACC_OVERWRITE is therefore accepted on a capturing stream only after an
+ * overwrite call on this plan captured into the same graph (each replay then
+ * restarts the integration); otherwise it returns BFX_ENOTSUP without
+ * enqueueing.                                                               */
 bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t ntime, void *d_acc,
                                   uint32_t flags, bfx_stream stream);
 
@@ -229,10 +235,38 @@ bfx_status bfx_fengine(const int8_t *d_in, int32_t ninput, int32_t nfft, int64_t
  * ntime must be a positive multiple of navg (<= 2^30); ninput a positive
  * multiple of 32 (<= 8192); nbeam in [1, 256].  binary16 products, binary32
  * accumulation of y and of P.  This build integrates navg = 1, 2, 4, 8, 16 or
- * 32 samples and returns BFX_ENOTSUP for other valid navg.                   */
+ * 32 samples and returns BFX_ENOTSUP for other valid navg, and for shapes
+ * needing more than (2^32-1)/256 workgroups (ceil(nchan/8)*8 *
+ * ceil(ntime/256) * ceil(nbeam/32)); split such a gulp in time.             */
 bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput, int32_t nchan,
                                int32_t nbeam, int64_t ntime, int32_t navg, float *d_out,
                                bfx_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Phase-and-sum beamformer on 4+4-bit voltages with integer weights (Sec. 6:
+ * the DRX pipeline's GPU beamformer consumes the 4+4 complex samples
+ * directly), square-law detection and integration (Sec. 4.1 detect and
+ * accumulate blocks).  Exact integer arithmetic up to one final conversion:
+ *   d_x     device ci4 [ntime][nchan][ninput] (layout above);
+ *   d_w     device int8 [nchan][nbeam][ninput][2] weights (re, im), any int8
+ *           value, applied without conjugation;
+ *   d_scale device float[nbeam], per-beam scale of the weights (the physical
+ *           weight of beam b is scale_b * w);
+ *   d_out   device float [nbeam][nchan][ntime/navg]:
+ *             y[b][f][t] = sum_i w[f][b][i] x[t][f][i]        (exact integers)
+ *             S[b][f][u] = sum_{t=u*navg}^{u*navg+navg-1} |y[b][f][t]|^2 (exact)
+ *             P[b][f][u] = (float)((double)scale_b * (double)scale_b * (double)S),
+ *           each conversion and product rounded to nearest even, in that order.
+ * ninput a positive multiple of 64 (<= 8192), nchan in [1, 65536], nbeam in
+ * [1, 256], ntime a positive multiple of navg (<= 2^30).  d_x and d_w 16-byte
+ * aligned, d_scale and d_out 4-byte aligned.  This build integrates navg = 1,
+ * 2, 4, ..., 64 samples and returns BFX_ENOTSUP for other valid navg, and for
+ * shapes needing more than (2^32-1)/256 workgroups (ceil(nchan/8)*8 *
+ * ceil(ntime/256) * ceil(nbeam/32)).  int8 MFMA with int32 accumulation:
+ * every partial sum is bounded by 2 * 8192 * 128 * 128 < 2^31.              */
+bfx_status bfx_beamform_ci4(const void *d_x, const int8_t *d_w, const float *d_scale, int32_t ninput,
+                            int32_t nchan, int32_t nbeam, int64_t ntime, int32_t navg, float *d_out,
+                            bfx_stream stream);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,7 @@ import re
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfx.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bfx.h")
+HEADER_PATHS = [HEADER_PATH, os.path.join(os.path.dirname(_HERE), "include", "bfx_probe.h")]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -63,6 +64,10 @@ _SIGS = {
     "bfx_xengine_dump": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "bfx_fengine": (_st, [_vp, _i32, _i32, _i64, _vp, _vp, ctypes.c_int, _vp]),
     "bfx_beamform_detect": (_st, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "bfx_beamform_ci4": (_st, [_vp, _vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "bfx_probe_mfma": (_st, [_i32, _i32, _i32, _vp, _vp]),
+    "bfx_probe_mfma_ops": (_i64, [_i32, _i32, _i32]),
+    "bfx_probe_read": (_st, [_vp, _i64, _i32, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -78,9 +83,11 @@ class BfxError(RuntimeError):
 
 
 def header_symbols():
-    """Names of the functions declared in include/bfx.h."""
-    with open(HEADER_PATH) as fh:
-        text = fh.read()
+    """Names of the functions declared in include/*.h."""
+    text = ""
+    for path in HEADER_PATHS:
+        with open(path) as fh:
+            text += fh.read()
     return sorted(set(re.findall(r"\b(bfx_\w+)\s*\(", text)))
 
 
@@ -234,6 +241,27 @@ def bfx_beamform_detect(d_x, d_w, ninput: int, nchan: int, nbeam: int, ntime: in
                         d_out, stream=None):
     _check(_lib.bfx_beamform_detect(_addr(d_x), _addr(d_w), ninput, nchan, nbeam, ntime, navg,
                                     _addr(d_out), _stream(stream)))
+
+
+def bfx_beamform_ci4(d_x, d_w, d_scale, ninput: int, nchan: int, nbeam: int, ntime: int, navg: int,
+                     d_out, stream=None):
+    _check(_lib.bfx_beamform_ci4(_addr(d_x), _addr(d_w), _addr(d_scale), ninput, nchan, nbeam, ntime,
+                                 navg, _addr(d_out), _stream(stream)))
+
+
+BFX_PROBE_MFMA_I8, BFX_PROBE_MFMA_F16 = 0, 1
+
+
+def bfx_probe_mfma(kind: int, iters: int, nblocks: int, d_sink, stream=None):
+    _check(_lib.bfx_probe_mfma(kind, iters, nblocks, _addr(d_sink), _stream(stream)))
+
+
+def bfx_probe_mfma_ops(kind: int, iters: int, nblocks: int) -> int:
+    return int(_lib.bfx_probe_mfma_ops(kind, iters, nblocks))
+
+
+def bfx_probe_read(d_buf, nbytes: int, nblocks: int, d_sink, stream=None):
+    _check(_lib.bfx_probe_read(_addr(d_buf), nbytes, nblocks, _addr(d_sink), _stream(stream)))
 
 
 # ------------------------------------------------------------------ conveniences

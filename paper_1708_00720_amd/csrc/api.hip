@@ -44,6 +44,12 @@ bool fengine_supported(int32_t ninput, int32_t nfft);
 hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t nchan,
                            int32_t nbeam, int64_t ntime, int32_t navg, float *out, hipStream_t s);
 bool beamform_supported(int32_t navg);
+int64_t beamform_units(int32_t nchan, int32_t nbeam, int64_t ntime);
+hipError_t launch_beamform_ci4(const void *x, const int8_t *w, const float *scale, int32_t ninput,
+                               int32_t nchan, int32_t nbeam, int64_t ntime, int32_t navg, float *out,
+                               hipStream_t s);
+bool beamform_ci4_supported(int32_t navg);
+int64_t beamform_ci4_units(int32_t nchan, int32_t nbeam, int64_t ntime);
 
 }  // namespace bfx
 
@@ -60,6 +66,10 @@ struct bfx_xengine {
     std::vector<Sub> subs;
     int64_t nacc;
     int variant;  // kernel variant (bfx_xengine_autotune)
+    // graph capture: id of the capture sequence in which an overwrite call
+    // was last recorded (valid when cap_set)
+    bool cap_set;
+    unsigned long long cap_id;
     // batched plans only: device unit table and work list
     BatchUnit *d_units;
     int2 *d_work;
@@ -272,6 +282,8 @@ bfx_status bfx_xengine_create(bfx_xengine **plan, int32_t ninput, int32_t nchan,
     p->batched = false;
     p->subs.push_back(Sub{ninput, nchan});
     p->nacc = 0;
+    p->cap_set = false;
+    p->cap_id = 0;
     p->d_units = nullptr;
     p->d_work = nullptr;
     p->nwork = 0;
@@ -302,6 +314,8 @@ bfx_status bfx_xengine_create_batched(bfx_xengine **plan, int32_t nsub, const in
     p->in = in;
     p->batched = true;
     p->nacc = 0;
+    p->cap_set = false;
+    p->cap_id = 0;
     p->d_units = nullptr;
     p->d_work = nullptr;
     for (int32_t k = 0; k < nsub; ++k) p->subs.push_back(Sub{ninput[k], nchan[k]});
@@ -503,7 +517,21 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
                     "%lld for this dtype; dump and start a new integration",
                     (long long)base, (long long)ntime, (long long)tmax);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
+    // Under stream capture the host-side bound is checked once, at capture,
+    // while every replay adds to d_acc again.  A captured call that adds is
+    // therefore accepted only after an overwrite call captured into the same
+    // graph: each replay then restarts the integration, and the samples of one
+    // replay are the nacc checked here.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    unsigned long long cap_id = 0;
+    hipError_t e = hipStreamGetCaptureInfo(s, &cap, &cap_id);
+    if (e != hipSuccess) return hip_fail(e, "querying the stream's capture state");
+    const bool capturing = cap == hipStreamCaptureStatusActive;
+    if (capturing && !overwrite && !(plan->cap_set && plan->cap_id == cap_id))
+        return fail(BFX_ENOTSUP,
+                    "an accumulate that adds (no BFX_ACC_OVERWRITE) may be captured into a graph "
+                    "only after an overwrite call captured into the same graph: replays would "
+                    "otherwise grow the integration past the checked bound");
     if (plan->in == BFX_CF16) {
         // binary32 accumulation has no integer bound; launches are still cut
         // at kLaunchMaxTime rows so the kernel's row counter stays 32-bit.
@@ -536,6 +564,10 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
     }
     if (e != hipSuccess) return hip_fail(e, "X-engine launch");
     plan->nacc = base + ntime;
+    if (capturing && overwrite) {
+        plan->cap_set = true;
+        plan->cap_id = cap_id;
+    }
     return BFX_OK;
 }
 
@@ -597,12 +629,42 @@ bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput,
     if (navg <= 0 || ntime <= 0 || ntime % navg || ntime > ((int64_t)1 << 30))
         return fail(BFX_EINVAL, "ntime=%lld must be a positive multiple of navg=%d, <= 2^30",
                     (long long)ntime, navg);
+    if (beamform_units(nchan, nbeam, ntime) > kMaxWorkgroups256)
+        return fail(BFX_ENOTSUP, "nchan=%d x nbeam=%d x ntime=%lld needs more workgroups than one "
+                                 "launch can hold; split the gulp in time",
+                    nchan, nbeam, (long long)ntime);
     if (!beamform_supported(navg))
         return fail(BFX_ENOTSUP, "this build integrates navg = 1, 2, 4, 8, 16 or 32 samples "
                                  "(got %d)", navg);
     hipError_t e = launch_beamform(d_x, d_w, ninput, nchan, nbeam, ntime, navg, d_out,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "beamformer launch");
+    return BFX_OK;
+}
+
+bfx_status bfx_beamform_ci4(const void *d_x, const int8_t *d_w, const float *d_scale, int32_t ninput,
+                            int32_t nchan, int32_t nbeam, int64_t ntime, int32_t navg, float *d_out,
+                            bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!d_x || !d_w || !d_scale || !d_out) return fail(BFX_EINVAL, "NULL buffer");
+    if (!aligned16(d_x) || !aligned16(d_w) || ((uintptr_t)d_scale & 3u) || ((uintptr_t)d_out & 3u))
+        return fail(BFX_EINVAL, "d_x and d_w must be 16-byte aligned, d_scale and d_out 4-byte aligned");
+    if (ninput <= 0 || ninput % 64 || ninput > 8192)
+        return fail(BFX_EINVAL, "ninput=%d must be a positive multiple of 64 <= 8192", ninput);
+    if (nchan <= 0 || nchan > 65536) return fail(BFX_EINVAL, "nchan=%d out of range", nchan);
+    if (nbeam <= 0 || nbeam > 256) return fail(BFX_EINVAL, "nbeam=%d must be in [1, 256]", nbeam);
+    if (navg <= 0 || ntime <= 0 || ntime % navg || ntime > ((int64_t)1 << 30))
+        return fail(BFX_EINVAL, "ntime=%lld must be a positive multiple of navg=%d, <= 2^30",
+                    (long long)ntime, navg);
+    if (!beamform_ci4_supported(navg))
+        return fail(BFX_ENOTSUP, "this build integrates navg = 1, 2, 4, ..., 64 samples (got %d)", navg);
+    if (beamform_ci4_units(nchan, nbeam, ntime) > kMaxWorkgroups256)
+        return fail(BFX_ENOTSUP, "nchan=%d x nbeam=%d x ntime=%lld needs more workgroups than one "
+                                 "launch can hold; split the gulp in time",
+                    nchan, nbeam, (long long)ntime);
+    hipError_t e = launch_beamform_ci4(d_x, d_w, d_scale, ninput, nchan, nbeam, ntime, navg, d_out,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ci4 beamformer launch");
     return BFX_OK;
 }
 

@@ -273,6 +273,14 @@ hipError_t set_attributes() {
 
 bool beamform_supported(int32_t navg) { return navg >= 1 && navg <= 32 && (navg & (navg - 1)) == 0; }
 
+// Workgroups of one launch: channels (padded to the XCD count) x 256-sample
+// units x 32-beam groups.
+int64_t beamform_units(int32_t nchan, int32_t nbeam, int64_t ntime) {
+    const int64_t ntb = (ntime + kTB - 1) / kTB;
+    const int64_t nbg = (nbeam + kBeams - 1) / kBeams;
+    return ((int64_t)nchan + 7) / 8 * 8 * ntb * nbg;
+}
+
 hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t nchan,
                            int32_t nbeam, int64_t ntime, int32_t navg, float *out, hipStream_t s) {
     const hipError_t e = g_init.ensure(set_attributes, nullptr);
@@ -281,7 +289,8 @@ hipError_t launch_beamform(const void *x, const void *w, int32_t ninput, int32_t
     while ((1 << lognavg) < navg) ++lognavg;
     const int ntb = (int)((ntime + kTB - 1) / kTB);
     const int nbg = (nbeam + kBeams - 1) / kBeams;
-    const int64_t units = ((int64_t)nchan + 7) / 8 * 8 * ntb * nbg;
+    const int64_t units = beamform_units(nchan, nbeam, ntime);
+    if (units > kMaxWorkgroups256) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(kKernels[lognavg], dim3((unsigned)units), dim3(kThreads), kLdsBytes, s,
                        (const uint8_t *)x, (const uint8_t *)w, ninput, nchan, nbeam, (int)ntime,
                        ntb, nbg, out);

@@ -1,0 +1,318 @@
+// Integer phase-and-sum beamformer on 4+4-bit voltages, with square-law
+// detection and time integration.  The DRX pipeline of Sec. 6 beamforms the
+// 4+4 complex samples directly, without an unpacking pass; the detect and
+// accumulate blocks are those of Sec. 4.1.
+//
+//   y[b][f][t] = sum_i w[f][b][i] x[t][f][i]          (complex, no conjugation)
+//   S[b][f][u] = sum_{t in window u} |y[b][f][t]|^2   (exact integers)
+//   P[b][f][u] = fl32(fl64(fl64(scale_b)^2) * fl64(S))
+//
+// Weights are int8 pairs (re, im) with a per-beam binary32 scale, so y and S
+// are exact integers and the only rounding is in the final conversion, taken
+// in the steps above: the result is the same bits whatever the launch shape.
+//
+// Formulation.  Per channel a (beams x inputs) by (inputs x time) complex
+// product, as four real products on v_mfma_i32_16x16x64_i8 with int32
+// accumulation and no negated operand (so the whole int8 weight range is
+// exact):
+//   RR = W_re X_re,  II = W_im X_im,  IM = W_re X_im + W_im X_re,
+//   Re y = RR - II,  Im y = IM.
+// A voltage row x[t][f][:] is one B column with K = inputs contiguous: lane
+// (column n, K group q) takes 16 consecutive bytes of one row.  The ci4 byte
+// is split in registers into 16*re (the high nibble kept in place) and 16*im
+// (the low nibble shifted up), as int8 bytes; the products carry a factor 16
+// that the epilogue shifts out exactly (RR, II, IM are multiples of 16).
+//
+// Data path.  Work unit = (channel, 256 samples, 32 beams); four waves, wave
+// w owns samples 64w .. 64w+63 of the unit (four tiles of 16) for all 32
+// beams (two M tiles).  A stage is 16 samples of every wave (64 time rows) x
+// one K chunk of up to 256 inputs, 256 bytes per LDS row; it reaches LDS with
+// global_load_lds_dwordx4 (each 1 KiB wave instruction is 4 whole rows).  The
+// 16-byte chunks of a row are XOR-swizzled by the row index, so the 16 rows
+// of one fragment read hit distinct banks.  Three stages rotate; the stage two
+// ahead is issued behind the barrier that releases the current one, across
+// K-chunk boundaries.  The weights of a K chunk (two M tiles x (re, im) x 4
+// K steps) are loaded into registers when the chunk starts.
+//
+// Detection.  In the 16x16 output layout a lane holds rows 4g..4g+3 (beams)
+// of one sample column, so |y|^2 is lane-local; a window of navg <= 16
+// samples is navg consecutive lanes of a 16-lane group, summed in int64 by a
+// ds_swizzle butterfly; navg = 32 and 64 also add the wave's adjacent tiles.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bfx_internal.h"
+
+namespace bfx {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kBeams = 32;             // beams per unit: two M tiles of 16
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTiles = 4;              // 16-sample tiles per wave and unit
+constexpr int kTB = 16 * kTiles * kWaves;  // samples per unit (256)
+constexpr int kRows = 16 * kWaves;     // time rows per stage
+constexpr int kKC = 256;               // inputs per K chunk (one LDS row)
+constexpr int kKS = kKC / 64;          // MFMA K steps per chunk
+constexpr int kStageBytes = kRows * kKC;  // 16 KiB
+constexpr int kSlots = 3;
+constexpr int kLdsBytes = kSlots * kStageBytes;
+constexpr int kDmaPerWave = kStageBytes / 1024 / kWaves;  // 4
+
+struct Unit {
+    int f, tb, bg;
+};
+
+// Flat unit id B -> (channel, 256-sample block, beam group); units of one
+// channel sit at B % 8 == f % 8 and so share an XCD and its L2 (the channel's
+// weights are fetched from HBM once).
+__device__ inline bool unit_of(int B, int ntb, int nbg, int nchan, Unit &u) {
+    const int s = B >> 3;
+    const int per = ntb * nbg;
+    const int cl = s / per;
+    const int r = s - cl * per;
+    u.bg = r / ntb;
+    u.tb = r - u.bg * ntb;
+    u.f = cl * 8 + (B & 7);
+    return u.f < nchan;
+}
+
+__device__ inline void dma16(const void *src, uint32_t lds_wave_base) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_wave_base)), "v"(src)
+                 : "memory", "m0");
+}
+
+template <int N>
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(N | 0x0F70); }
+
+// Workgroup barrier without a memory fence: the DMA into LDS is ordered by
+// the explicit vmcnt waits, and every LDS read of a stage has returned (its
+// MFMAs consumed it) before the wave reaches the next barrier.
+__device__ inline void block_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Lane exchange by xor within 32-lane groups (ds_swizzle bitmask mode).
+template <int K>
+__device__ inline int swz_xor(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x1F | (K << 10)); }
+
+template <int K>
+__device__ inline int64_t swz_xor64(int64_t v) {
+    const int lo = swz_xor<K>((int)(uint32_t)v);
+    const int hi = swz_xor<K>((int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over aligned groups of 2^L consecutive lanes (L <= 4), in int64.
+template <int L>
+__device__ inline int64_t group_sum64(int64_t p) {
+    if constexpr (L >= 1) p += swz_xor64<1>(p);
+    if constexpr (L >= 2) p += swz_xor64<2>(p);
+    if constexpr (L >= 3) p += swz_xor64<4>(p);
+    if constexpr (L >= 4) p += swz_xor64<8>(p);
+    return p;
+}
+
+// This wave's share of the DMA of stage i (K chunk i / kTiles, tile i %
+// kTiles).  LDS row R = 16 v + r holds time tu + 64 v + 16 s + r of wave v
+// (clamped to the last sample: rows past ntime feed windows never stored),
+// bytes kc .. kc + 255 of the channel's row, its 16-byte chunk c at slot
+// c ^ (R & 15).  Slots beyond the chunk's inputs fetch chunk 0 of the row
+// (never read).
+__device__ __forceinline__ void stage_dma(const uint8_t *xf, int64_t rstride, int tu, int ntime, int ninput,
+                                          int i, uint32_t lds_stage, int wave, int lane) {
+    const int kc = (i / kTiles) * kKC;
+    const int s = i % kTiles;
+    const int cpr = min(kKC, ninput - kc) / 16;
+#pragma unroll
+    for (int j = 0; j < kDmaPerWave; ++j) {
+        const int ins = wave * kDmaPerWave + j;  // 1 KiB = LDS rows 4 ins .. 4 ins + 3
+        const int R = 4 * ins + (lane >> 4);
+        const int c = (lane & 15) ^ (R & 15);
+        const int t = min(tu + 64 * (R >> 4) + 16 * s + (R & 15), ntime - 1);
+        const int cc = c < cpr ? c : 0;
+        dma16(xf + (int64_t)t * rstride + kc + 16 * cc, lds_stage + 1024 * ins);
+    }
+}
+
+__device__ __forceinline__ void split_ci4(const v4i raw, v4i &re, v4i &im) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        re[k] = (int)((uint32_t)raw[k] & 0xF0F0F0F0u);
+        im[k] = (int)(((uint32_t)raw[k] << 4) & 0xF0F0F0F0u);
+    }
+}
+
+template <int LOGNAVG>
+__global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
+    const uint8_t *__restrict__ x, const int8_t *__restrict__ w, const float *__restrict__ scale,
+    int ninput, int nchan, int nbeam, int ntime, int ntb, int nbg, float *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
+    Unit u;
+    if (!unit_of(blockIdx.x, ntb, nbg, nchan, u)) return;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int m = lane & 15;  // A row (beam within an M tile) / B column (sample)
+    const int q = lane >> 4;  // K group of 16 inputs; output rows 4q..4q+3
+
+    const int64_t rstride = (int64_t)nchan * ninput;
+    const int tu = u.tb * kTB;
+    const uint8_t *xf = x + (int64_t)u.f * ninput;
+    const int nchunk = (ninput + kKC - 1) / kKC;
+    const int nst = nchunk * kTiles;
+
+    v4i rr[kTiles][2], ii[kTiles][2], im[kTiles][2];
+#pragma unroll
+    for (int s = 0; s < kTiles; ++s)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) rr[s][mt] = ii[s][mt] = im[s][mt] = v4i{0, 0, 0, 0};
+
+    // LDS row of this lane's B fragments, and its swizzle
+    const int R = 16 * wave + m;
+    const int swz = R & 15;
+
+#pragma unroll
+    for (int i = 0; i < kSlots - 1; ++i)
+        if (i < nst) stage_dma(xf, rstride, tu, ntime, ninput, i, lds_base + i * kStageBytes, wave, lane);
+
+    v4i wre[kKS][2], wim[kKS][2];
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int kc = ch * kKC;
+        const int nks = min(kKC, ninput - kc) / 64;
+        // weights of this K chunk: beam bg*32 + 16 mt + m, inputs
+        // kc + 64 ks + 16 q .. +15, de-interleaved into re and im bytes
+#pragma unroll
+        for (int ks = 0; ks < kKS; ++ks)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const int beam = u.bg * kBeams + 16 * mt + m;
+                v4i a = v4i{0, 0, 0, 0}, b = v4i{0, 0, 0, 0};
+                if (ks < nks && beam < nbeam) {
+                    const int8_t *p = w + (((int64_t)u.f * nbeam + beam) * ninput + kc + 64 * ks + 16 * q) * 2;
+                    a = *(const v4i *)p;
+                    b = *(const v4i *)(p + 16);
+                }
+                wre[ks][mt] = v4i{(int)__builtin_amdgcn_perm(a[1], a[0], 0x06040200u),
+                                  (int)__builtin_amdgcn_perm(a[3], a[2], 0x06040200u),
+                                  (int)__builtin_amdgcn_perm(b[1], b[0], 0x06040200u),
+                                  (int)__builtin_amdgcn_perm(b[3], b[2], 0x06040200u)};
+                wim[ks][mt] = v4i{(int)__builtin_amdgcn_perm(a[1], a[0], 0x07050301u),
+                                  (int)__builtin_amdgcn_perm(a[3], a[2], 0x07050301u),
+                                  (int)__builtin_amdgcn_perm(b[1], b[0], 0x07050301u),
+                                  (int)__builtin_amdgcn_perm(b[3], b[2], 0x07050301u)};
+            }
+#pragma unroll
+        for (int s = 0; s < kTiles; ++s) {
+            const int i = ch * kTiles + s;
+            // stage i has landed everywhere; the slot of stage i - 1 is free
+            if (i + 1 < nst) wait_vm<kDmaPerWave>();
+            else wait_vm<0>();
+            block_barrier();
+            if (i + kSlots - 1 < nst)
+                stage_dma(xf, rstride, tu, ntime, ninput, i + kSlots - 1,
+                          lds_base + ((i + kSlots - 1) % kSlots) * kStageBytes, wave, lane);
+            const uint8_t *srow = lds + (i % kSlots) * kStageBytes + R * kKC;
+            v4i raw[kKS];
+#pragma unroll
+            for (int ks = 0; ks < kKS; ++ks)
+                if (ks < nks) raw[ks] = *(const v4i *)(srow + 16 * ((4 * ks + q) ^ swz));
+#pragma unroll
+            for (int ks = 0; ks < kKS; ++ks) {
+                if (ks < nks) {
+                    v4i xr, xi;
+                    split_ci4(raw[ks], xr, xi);
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        rr[s][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wre[ks][mt], xr, rr[s][mt], 0, 0, 0);
+                        ii[s][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wim[ks][mt], xi, ii[s][mt], 0, 0, 0);
+                        im[s][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wre[ks][mt], xi, im[s][mt], 0, 0, 0);
+                        im[s][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wim[ks][mt], xr, im[s][mt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+
+    // detect and integrate: lane holds sample tu + 64 wave + 16 s + m of beams
+    // bg*32 + 16 mt + 4q + v
+    constexpr int L = LOGNAVG < 4 ? LOGNAVG : 4;
+    constexpr int kTilesPerWin = LOGNAVG > 4 ? 1 << (LOGNAVG - 4) : 1;
+    const int nwin = ntime >> LOGNAVG;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int beam = u.bg * kBeams + 16 * mt + 4 * q + v;
+            const double sb = (double)(beam < nbeam ? scale[beam] : 0.0f);
+            const double sb2 = sb * sb;
+#pragma unroll
+            for (int s0 = 0; s0 < kTiles; s0 += kTilesPerWin) {
+                int64_t acc = 0;
+#pragma unroll
+                for (int s = s0; s < s0 + kTilesPerWin; ++s) {
+                    const int yr = (rr[s][mt][v] - ii[s][mt][v]) >> 4;
+                    const int yi = im[s][mt][v] >> 4;
+                    acc += (int64_t)yr * yr + (int64_t)yi * yi;
+                }
+                acc = group_sum64<L>(acc);
+                const int t = tu + 64 * wave + 16 * s0 + m;
+                const int uwin = t >> LOGNAVG;
+                if ((m & ((1 << L) - 1)) == 0 && uwin < nwin && beam < nbeam)
+                    out[((int64_t)beam * nchan + u.f) * nwin + uwin] = (float)(sb2 * (double)acc);
+            }
+        }
+    }
+}
+
+typedef void (*BfKernel)(const uint8_t *, const int8_t *, const float *, int, int, int, int, int, int,
+                         float *);
+const BfKernel kKernels[7] = {beamform_ci4_kernel<0>, beamform_ci4_kernel<1>, beamform_ci4_kernel<2>,
+                              beamform_ci4_kernel<3>, beamform_ci4_kernel<4>, beamform_ci4_kernel<5>,
+                              beamform_ci4_kernel<6>};
+
+DeviceInit g_init;
+
+hipError_t set_attributes() {
+    for (BfKernel k : kKernels) {
+        const hipError_t e =
+            hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool beamform_ci4_supported(int32_t navg) { return navg >= 1 && navg <= 64 && (navg & (navg - 1)) == 0; }
+
+int64_t beamform_ci4_units(int32_t nchan, int32_t nbeam, int64_t ntime) {
+    const int64_t ntb = (ntime + kTB - 1) / kTB;
+    const int64_t nbg = (nbeam + kBeams - 1) / kBeams;
+    return ((int64_t)nchan + 7) / 8 * 8 * ntb * nbg;
+}
+
+hipError_t launch_beamform_ci4(const void *x, const int8_t *w, const float *scale, int32_t ninput,
+                               int32_t nchan, int32_t nbeam, int64_t ntime, int32_t navg, float *out,
+                               hipStream_t s) {
+    const hipError_t e = g_init.ensure(set_attributes, nullptr);
+    if (e != hipSuccess) return e;
+    int lognavg = 0;
+    while ((1 << lognavg) < navg) ++lognavg;
+    const int ntb = (int)((ntime + kTB - 1) / kTB);
+    const int nbg = (nbeam + kBeams - 1) / kBeams;
+    const int64_t units = beamform_ci4_units(nchan, nbeam, ntime);
+    if (units > kMaxWorkgroups256) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kKernels[lognavg], dim3((unsigned)units), dim3(kThreads), kLdsBytes, s,
+                       (const uint8_t *)x, w, scale, ninput, nchan, nbeam, (int)ntime, ntb, nbg, out);
+    return hipGetLastError();
+}
+
+}  // namespace bfx

@@ -39,6 +39,10 @@ struct DeviceInit {
     }
 };
 
+// Largest grid of 256-lane workgroups one launch can take: the total lane
+// count of a grid dimension must stay below 2^32.
+constexpr int64_t kMaxWorkgroups256 = (((int64_t)1 << 32) - 1) / 256;
+
 // Thread-local error detail; returns `s` for convenient `return fail(...)`.
 bfx_status fail(bfx_status s, const char *fmt, ...);
 bfx_status hip_fail(hipError_t e, const char *what);

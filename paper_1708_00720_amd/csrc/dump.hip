@@ -4,7 +4,7 @@
 // of the accumulator, 2 x 16-byte read-modify-write of the running sum per
 // thread.  One group of four elements per thread: a grid that covers the
 // buffer keeps more loads in flight than a capped grid-stride loop (5.4 vs
-// 5.0 TB/s on 2048 x 131,328 cf32); the loop only strides beyond 2^24
+// 5.0 TB/s on 2048 x 131,328 cf32); the loop only strides beyond 2^23
 // workgroups.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -53,7 +53,8 @@ hipError_t launch_dump(bool is_int, const void *acc, void *out, double *run64, i
                        hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n / 4 + 255) / 256;
-    if (blocks > ((int64_t)1 << 24)) blocks = (int64_t)1 << 24;  // grid-stride beyond
+    // grid-stride beyond 2^23 workgroups (2^31 lanes, inside a launch's limit)
+    if (blocks > ((int64_t)1 << 23)) blocks = (int64_t)1 << 23;
     if (blocks < 1) blocks = 1;
     if (is_int)
         hipLaunchKernelGGL(dump_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, acc, out,

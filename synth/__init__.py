@@ -156,6 +156,22 @@ def steering_weights(seed, nchan: int, nbeam: int, ninput: int):
     return np.stack([np.cos(th), np.sin(th)], axis=-1).astype(np.float16)
 
 
+def int8_steering_weights(seed, nchan: int, nbeam: int, ninput: int, amp: float = 127.0):
+    """Unit-modulus weights quantized to int8: [F][B][N][2] = rint(amp cos theta),
+    rint(amp sin theta), theta ~ U[0, 2pi); with the per-beam scale 1/amp
+    (float32 [B]) they stand for the unit-modulus weights."""
+    rng = rng_for(seed, 2)
+    th = rng.uniform(0.0, 2.0 * np.pi, size=(nchan, nbeam, ninput))
+    w = np.stack([np.rint(amp * np.cos(th)), np.rint(amp * np.sin(th))], axis=-1).astype(np.int8)
+    return w, np.full(nbeam, 1.0 / amp, np.float32)
+
+
+def extreme_int8_weights(seed, nchan: int, nbeam: int, ninput: int):
+    """int8 weights [F][B][N][2] uniform over the whole code range, -128 included."""
+    rng = rng_for(seed, 3)
+    return rng.integers(-128, 128, size=(nchan, nbeam, ninput, 2)).astype(np.int8)
+
+
 # --------------------------------------------------------------------------
 # Batched mixed-size subarrays
 

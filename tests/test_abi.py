@@ -128,6 +128,14 @@ def test_beamform_argument_errors(kw):
     assert ei.value.status == bfx.BFX_EINVAL
 
 
+def test_beamform_rejects_grids_beyond_one_launch():
+    # 65536 channels x 2^22 units of 256 samples x 8 beam groups: 2^43 workgroups
+    with pytest.raises(bfx.BfxError) as ei:
+        bfx.bfx_beamform_detect(FAKE, FAKE, 64, 65536, 256, 1 << 30, 16, FAKE, stream=0)
+    assert ei.value.status == bfx.BFX_ENOTSUP
+    assert "workgroups" in ei.value.detail
+
+
 @pytest.mark.parametrize("navg", [3, 64, 128])
 def test_beamform_unsupported_navg(navg):
     with pytest.raises(bfx.BfxError) as ei:
@@ -142,3 +150,19 @@ def test_batched_create_validation_host_side():
     with pytest.raises(bfx.BfxError) as ei:
         bfx.bfx_xengine_create_batched([32], [4], "cf16")
     assert ei.value.status == bfx.BFX_ENOTSUP
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ninput=96), bfx.BFX_EINVAL), (dict(ninput=0), bfx.BFX_EINVAL),
+    (dict(nbeam=0), bfx.BFX_EINVAL), (dict(nbeam=257), bfx.BFX_EINVAL),
+    (dict(ntime=24), bfx.BFX_EINVAL), (dict(nchan=0), bfx.BFX_EINVAL),
+    (dict(navg=128, ntime=256), bfx.BFX_ENOTSUP), (dict(navg=3, ntime=48), bfx.BFX_ENOTSUP),
+    (dict(nchan=65536, nbeam=256, ntime=1 << 30, navg=64), bfx.BFX_ENOTSUP),
+])
+def test_beamform_ci4_argument_errors(kw, code):
+    args = dict(ninput=64, nchan=2, nbeam=4, ntime=32, navg=16)
+    args.update(kw)
+    with pytest.raises(bfx.BfxError) as ei:
+        bfx.bfx_beamform_ci4(FAKE, FAKE, FAKE, args["ninput"], args["nchan"], args["nbeam"],
+                             args["ntime"], args["navg"], FAKE, stream=0)
+    assert ei.value.status == code

@@ -1,0 +1,71 @@
+"""GPU parity of the integer beamformer on 4+4-bit voltages (bfx_beamform_ci4)
+against the oracle: bit-exact binary32 beam power.
+
+The beams y and the detected sums S are exact integers on both sides and the
+one conversion P = fl32(fl64(scale^2) * fl64(S)) takes the same rounding
+steps, so every output word must be equal.  Cases: extreme codes (-8 voltages,
+-128 weights) over ragged shapes and every navg, a sum S above 2^53 (where the
+conversion to double rounds), and the full workload (512 inputs, 2048
+channels, 1024 samples, 32 beams, navg 16) on sampled channels.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import banner, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(x, w, scale, N, F, B, T, navg):
+    import torch
+    import paper_1708_00720_amd as bfx
+    out = torch.full((B * F * (T // navg),), float("nan"), dtype=torch.float32, device="cuda")
+    bfx.bfx_beamform_ci4(to_dev(x), to_dev(w), torch.from_numpy(np.asarray(scale, np.float32)).cuda(),
+                         N, F, B, T, navg, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(B, F, T // navg)
+
+
+@pytest.mark.parametrize("N,F,B,T,navg", [
+    (64, 1, 1, 16, 16), (64, 3, 5, 48, 1), (128, 2, 32, 256, 2), (192, 5, 33, 320, 4),
+    (320, 3, 40, 512, 8), (512, 9, 64, 272, 16), (256, 4, 7, 640, 32), (448, 2, 16, 768, 64),
+])
+def test_extreme_codes_ragged(N, F, B, T, navg):
+    banner(f"beamform_ci4 extremes N={N} F={F} B={B} T={T} navg={navg}")
+    x = synth.extreme_voltages(300 + N + B, T, F, N, "ci4")
+    w = synth.extreme_int8_weights(400 + T, F, B, N)
+    scale = np.random.default_rng(N * B).uniform(0.001, 3.0, B).astype(np.float32)
+    got = _run(x, w, scale, N, F, B, T, navg)
+    want = oracle.beamform_ci4(x, w, scale, navg)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_most_negative_codes_large_sums():
+    """Every voltage -8-8i and every weight -128-128i at the largest input
+    count: y = -128 * 8 * 8192 * 2i per sample, and the window sum over 64
+    samples (1.8e16) lies above 2^53, where the conversion to double rounds."""
+    N, F, B, T, navg = 8192, 1, 3, 128, 64
+    banner(f"beamform_ci4 most negative codes N={N} navg={navg}")
+    x = synth.constant_voltages(T, F, N, "ci4", -8, -8)
+    w = np.full((F, B, N, 2), -128, np.int8)
+    scale = np.array([1.0, 0.1, 3.0e-5], np.float32)
+    got = _run(x, w, scale, N, F, B, T, navg)
+    want = oracle.beamform_ci4(x, w, scale, navg)
+    S = navg * (2 * 128 * 8 * N) ** 2
+    assert S > 2 ** 53
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_full_size_sampled_channels():
+    """512 inputs, 2048 channels, 1024 samples, 32 quantized unit-modulus
+    beams, navg 16: sampled channels bit-exact against the oracle."""
+    N, F, B, T, navg = 512, 2048, 32, 1024, 16
+    banner(f"beamform_ci4 full size N={N} F={F} B={B} T={T} navg={navg}")
+    x = synth.voltages(9, T, F, N, "ci4", 2.5, 7)
+    w, scale = synth.int8_steering_weights(10, F, B, N)
+    got = _run(x, w, scale, N, F, B, T, navg)
+    for f in (0, 1, 7, 8, 1000, 2047):
+        want = oracle.beamform_ci4(np.ascontiguousarray(x[:, f:f + 1]), w[f:f + 1], scale, navg)
+        assert np.array_equal(got[:, f:f + 1].view(np.uint32), want.view(np.uint32)), f

@@ -6,15 +6,19 @@
   except at near-ties where the binary32 transform may round the other way,
   which must differ by exactly one code.  The tie window comes from an a priori
   error bound of the binary32 FFT, not from the GPU's output;
-* the F -> X chain on a bin-centred tone with per-input delays reproduces the
-  closed-form visibility magnitude and phase slope.
+* the F+X workload (256 inputs, 512 frames) in stages: binary32 spectra on
+  sampled frames and inputs; every ci8 code of two whole frames; the integer
+  X-engine on the GPU's own ci8 spectra, bit-exact against the oracle on the
+  same bytes; and the closed-form visibility magnitude and phase slope of a
+  bin-centred tone with per-input delays.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_util import banner, to_dev
+from fx_checks import freivalds_check
+from gpu_util import banner, packed_vis, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -79,37 +83,75 @@ def _tie_window(x_block):
     return 8 * 12 * U32 * np.linalg.norm(x_block.astype(np.float64))
 
 
-def test_ci8_equal_except_flagged_near_ties():
-    ninput, nspec = 32, 4
-    banner(f"fengine ci8 ninput={ninput} nspec={nspec}")
-    x, _ = synth.adc_tone(32, ninput, NFFT, nspec)
-    scale = synth.fengine_scale(NCHAN)
-    got = _run_f(x, ninput, nspec, scale, "ci8")
-    nflag = nmiss = 0
-    total = 0
-    for s in range(nspec):
-        X = oracle.dft_real(np.ascontiguousarray(x[s * NFFT:(s + 1) * NFFT]), NFFT)  # [1][2048][N][2]
-        q = oracle.requantize(X, scale)[0]                                             # [2048][N][2]
-        for i in range(ninput):
-            win = _tie_window(x[s * NFFT:(s + 1) * NFFT, i]) * float(scale[0])
-            prod = X[0, :, i, :] * scale[:, None].astype(np.float64)
+def _check_ci8_codes(x, got, scale, frames, inputs):
+    """ci8 codes of the GPU against the oracle's requantizer on the double
+    spectrum.  A code may differ only where s*v lies within the a priori
+    binary32 error of a half-integer: the FFT bound scaled by s, plus the
+    rounding of the binary32 product s*v itself (u |s v|).  Such codes must
+    differ by exactly one.  Returns (codes, flagged, differing)."""
+    nflag = nmiss = total = 0
+    for s in frames:
+        blk = np.ascontiguousarray(x[s * NFFT:(s + 1) * NFFT][:, inputs])
+        X = oracle.dft_real(blk, NFFT)                      # [1][2048][n][2]
+        q = oracle.requantize(X, scale)[0]                  # [2048][n][2]
+        for col, i in enumerate(inputs):
+            prod = X[0, :, col, :] * scale[:, None].astype(np.float64)
+            win = _tie_window(blk[:, col]) * float(scale[0]) + U32 * np.abs(prod)
             near = np.abs(np.abs(prod - np.floor(prod)) - 0.5) < win
-            diff = got[s, :, i, :].astype(int) - q[:, i, :].astype(int)
+            diff = got[s, :, i, :].astype(int) - q[:, col, :].astype(int)
             total += diff.size
             nflag += int(near.sum())
             bad = (diff != 0) & ~near
             assert not bad.any(), (s, i, np.argwhere(bad)[:5])
             assert np.all(np.abs(diff[near]) <= 1)
             nmiss += int((diff != 0).sum())
+    return total, nflag, nmiss
+
+
+def test_ci8_equal_except_flagged_near_ties():
+    ninput, nspec = 32, 4
+    banner(f"fengine ci8 ninput={ninput} nspec={nspec}")
+    x, _ = synth.adc_tone(32, ninput, NFFT, nspec)
+    scale = synth.fengine_scale(NCHAN)
+    got = _run_f(x, ninput, nspec, scale, "ci8")
+    total, nflag, nmiss = _check_ci8_codes(x, got, scale, range(nspec), list(range(ninput)))
     print(f"{total} codes, {nflag} inside the tie window, {nmiss} differ by one")
     assert got.min() >= -127  # saturation never emits -128
 
 
-def test_full_size_sampled_spectra():
+@pytest.fixture(scope="module")
+def fx_full():
+    """The F+X workload run once on the GPU: 256 real inputs x 512 frames of
+    4096 (noise sigma 16 plus a unit tone at channel 777 with per-input
+    delays), F-engine to ci8, then the integer X-engine over the 512 spectra
+    of every channel.  Returns the input, the delays, the GPU's ci8 spectra
+    and its visibilities (host copies)."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    ninput, nspec = 256, 512
+    banner("F+X full size: fengine ci8 -> xengine ci8 (256 inputs, 2048 ch, 512 spectra)")
+    x, tau = synth.adc_tone(3, ninput, NFFT, nspec)
+    scale = synth.fengine_scale(NCHAN)
+    d_in = to_dev(x)
+    d_scale = torch.from_numpy(scale).cuda()
+    spec = torch.zeros(nspec * NCHAN * ninput * 2, dtype=torch.int8, device="cuda")
+    bfx.bfx_fengine(d_in, ninput, NFFT, nspec, d_scale, spec, out="ci8")
+    plan = bfx.bfx_xengine_create(ninput, NCHAN, "ci8")
+    vis = bfx.visibilities_buffer(plan)
+    bfx.bfx_xengine_accumulate(plan, spec, nspec, vis, overwrite=True)
+    torch.cuda.synchronize()
+    plan.close()
+    spec_h = spec.cpu().numpy().reshape(nspec, NCHAN, ninput, 2)
+    vis_h = packed_vis(vis, NCHAN, ninput)
+    del d_in, spec, vis
+    return dict(x=x, tau=tau, scale=scale, spec=spec_h, vis=vis_h, ninput=ninput, nspec=nspec)
+
+
+def test_full_size_sampled_spectra(fx_full):
     """256 inputs, 512 frames (the F+X configuration), binary32 spectrum sampled."""
     ninput, nspec = 256, 512
     banner(f"fengine cf32 full size ninput={ninput} nspec={nspec}")
-    x, _ = synth.adc_tone(3, ninput, NFFT, nspec)
+    x = fx_full["x"]
     got = _run_f(x, ninput, nspec, np.ones(NCHAN), "cf32")
     frames = (0, 7, 8, 255, 511)
     inputs = [0, 1, 15, 16, 17, 128, 254, 255]
@@ -122,44 +164,62 @@ def test_full_size_sampled_spectra():
     assert worst <= 1e-6
 
 
-def test_fx_chain_tone_closed_form():
-    """F -> ci8 -> X-engine: a unit tone at channel 777 with per-input delays.
+def test_fx_ci8_full_size_near_ties(fx_full):
+    """Stage (ii) at the F+X size: every code of frames 0 and 511 (all 256
+    inputs) equals the oracle's, except flagged near-ties (off by one)."""
+    d = fx_full
+    banner("F+X stage ii: ci8 codes, frames 0 and 511, 256 inputs")
+    total, nflag, nmiss = _check_ci8_codes(d["x"], d["spec"], d["scale"], (0, d["nspec"] - 1),
+                                           list(range(d["ninput"])))
+    print(f"{total} codes, {nflag} inside the tie window, {nmiss} differ by one")
+    assert d["spec"].min() >= -127
+
+
+def test_fx_xengine_on_gpu_ci8_bit_exact(fx_full):
+    """Stage (iii): the X-engine on the GPU's own ci8 spectra equals the integer
+    oracle on those same bytes -- element by element on sampled channels
+    (including the tone channel), and through the exact Freivalds identity on
+    all 2048 channels."""
+    d = fx_full
+    spec, vis, N, S = d["spec"], d["vis"], d["ninput"], d["nspec"]
+    banner("F+X stage iii: X-engine on the GPU's ci8 vs the oracle")
+    raw = np.ascontiguousarray(spec)  # [S][F][N][2] int8 = the X-engine's [t][f][i] ci8
+    for f in (0, 1, 776, 777, 1024, 2047):
+        want = oracle.xengine_int(raw, "ci8", S, NCHAN, N, chans=(f, 1))
+        assert np.array_equal(vis[f], want[0]), f
+    re, im = spec[..., 0], spec[..., 1]
+    assert freivalds_check(vis, re, im, seed=11)
+
+
+def test_fx_chain_tone_closed_form(fx_full):
+    """Stage (iv): a unit tone at channel 777 with per-input delays.
 
     After scaling the tone has amplitude 2048 * s per component pair; the
     visibility at 777 is E[V_ij] = T (2048 s)^2 exp(-2 pi i 777 (tau_i - tau_j) / 4096).
     """
-    import torch
-    import paper_1708_00720_amd as bfx
-    ninput, nspec, k0 = 256, 512, 777
-    banner("fengine -> xengine tone closed form")
-    x, tau = synth.adc_tone(3, ninput, NFFT, nspec)
-    scale = synth.fengine_scale(NCHAN)
-    d_in = to_dev(x)
-    d_scale = torch.from_numpy(scale).cuda()
-    spec = torch.zeros(nspec * NCHAN * ninput * 2, dtype=torch.int8, device="cuda")
-    bfx.bfx_fengine(d_in, ninput, NFFT, nspec, d_scale, spec, out="ci8")
-    plan = bfx.bfx_xengine_create(ninput, NCHAN, "ci8")
-    vis = bfx.visibilities_buffer(plan)
-    bfx.bfx_xengine_accumulate(plan, spec, nspec, vis, overwrite=True)
-    torch.cuda.synchronize()
-    P = ninput * (ninput + 1) // 2
-    V = vis.view(NCHAN, P, 2)[k0].cpu().numpy().astype(np.float64)
-    a = 2048.0 * float(scale[0])
+    d = fx_full
+    ninput, nspec, k0, tau = d["ninput"], d["nspec"], 777, d["tau"]
+    banner("F+X stage iv: tone closed form")
+    V = d["vis"][k0].astype(np.float64)
+    a = 2048.0 * float(d["scale"][0])
     expect_mag = nspec * a * a
     # noise std of a cross visibility: sqrt(T (sigma_q^4 + 2 sigma_q^2 a^2)), sigma_q^2 = 64*2
     sq2 = 2 * 64.0
     sd = np.sqrt(nspec * (sq2 * sq2 / 2 + 2 * (sq2 / 2) * a * a))
     slope = -2 * np.pi * k0 / NFFT
-    res, dts, phs = [], [], []
-    for i in range(1, ninput, 7):
-        for j in range(0, i, 5):
-            z = V[i * (i + 1) // 2 + j, 0] + 1j * V[i * (i + 1) // 2 + j, 1]
-            pred = expect_mag * np.exp(1j * slope * (tau[i] - tau[j]))
-            res.append(abs(z - pred) / sd)
-            dts.append(tau[i] - tau[j])
-            phs.append(np.angle(z / np.exp(1j * slope * (tau[i] - tau[j]))))
-    res = np.array(res)
-    print(f"{len(res)} pairs, max |V - E[V]| / sd = {res.max():.2f}, median {np.median(res):.2f}")
-    assert res.max() < 6.0
-    assert abs(np.median(np.array(phs))) < 0.01  # phase residual after removing the slope
-    plan.close()
+    ii, jj = np.tril_indices(ninput, -1)
+    z = V[ii * (ii + 1) // 2 + jj, 0] + 1j * V[ii * (ii + 1) // 2 + jj, 1]
+    rot = np.exp(1j * slope * (tau[ii] - tau[jj]))
+    res = np.abs(z - expect_mag * rot) / sd
+    phs = np.angle(z / rot)
+    print(f"{res.size} pairs, max |V - E[V]| / sd = {res.max():.2f}, median {np.median(res):.2f}")
+    assert res.max() < 6.5
+    assert abs(np.median(phs)) < 0.01  # phase residual after removing the slope
+    # fitted phase slope over all cross pairs: the model slope plus the
+    # least-squares slope of the residual phase against the delay difference
+    # (no wrapping while the model is within pi / 50 rad per sample)
+    dt = tau[ii] - tau[jj]
+    resid = np.angle(z / rot)
+    est = slope + np.sum(resid * dt) / np.sum(dt * dt)
+    print(f"fitted phase slope {est:.5f} rad/sample (model {slope:.5f})")
+    assert abs(est / slope - 1) < 0.01

@@ -110,6 +110,80 @@ def test_ci8_bound_exact_at_tmax_and_rejected_beyond():
     p2.close()
 
 
+def test_bound_is_cumulative_across_add_calls():
+    """Two adding calls whose sum passes T_max: the second is rejected before
+    launch and leaves nacc and the visibilities as they were; a call that
+    lands exactly on T_max is accepted and exact."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    N, F = 4, 1
+    tmax = bfx.bfx_xengine_max_ntime("ci8")
+    banner(f"xengine ci8 cumulative bound over add calls, T_max={tmax}")
+    raw = synth.constant_voltages(tmax, F, N, "ci8", -128, -128)
+    d = to_dev(raw)
+    plan = bfx.bfx_xengine_create(N, F, "ci8")
+    acc = bfx.visibilities_buffer(plan)
+    bfx.bfx_xengine_accumulate(plan, d, 40000, acc, overwrite=True)
+    with pytest.raises(bfx.BfxError) as ei:
+        bfx.bfx_xengine_accumulate(plan, d, 30000, acc, overwrite=False)
+    assert ei.value.status == bfx.BFX_ERANGE
+    assert bfx.bfx_xengine_nacc(plan) == 40000
+    bfx.bfx_xengine_accumulate(plan, d, tmax - 40000, acc, overwrite=False)
+    assert bfx.bfx_xengine_nacc(plan) == tmax
+    with pytest.raises(bfx.BfxError) as ei:
+        bfx.bfx_xengine_accumulate(plan, d, 1, acc, overwrite=False)
+    assert ei.value.status == bfx.BFX_ERANGE
+    torch.cuda.synchronize()
+    got = packed_vis(acc, F, N)
+    assert np.all(got[..., 0] == tmax * 2 * 128 * 128) and np.all(got[..., 1] == 0)
+    plan.close()
+
+
+def test_graph_capture_needs_an_overwrite_anchor():
+    """An adding accumulate captured without a preceding captured overwrite is
+    rejected (replays would grow the integration unchecked); a captured
+    overwrite + add sequence replays exactly, with fresh data between
+    replays."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    T, F, N = 64, 3, 72
+    banner("xengine ci8 graph capture: overwrite anchor")
+    plan = bfx.bfx_xengine_create(N, F, "ci8")
+    a = torch.zeros(bfx.bfx_xengine_in_bytes(plan, T), dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    acc = bfx.visibilities_buffer(plan)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up outside capture (kernel attributes)
+        bfx.bfx_xengine_accumulate(plan, a, T, acc, overwrite=True)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g0 = torch.cuda.CUDAGraph()
+    err = None
+    with torch.cuda.graph(g0):
+        try:
+            bfx.bfx_xengine_accumulate(plan, a, T, acc, overwrite=False)
+        except bfx.BfxError as e:
+            err = e
+    assert err is not None and err.status == bfx.BFX_ENOTSUP
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bfx.bfx_xengine_accumulate(plan, a, T, acc, overwrite=True)
+        bfx.bfx_xengine_accumulate(plan, b, T, acc, overwrite=False)
+    assert bfx.bfx_xengine_nacc(plan) == 2 * T
+    for rep in range(3):
+        ga = synth.extreme_voltages(700 + rep, T, F, N, "ci8")
+        gb = synth.extreme_voltages(710 + rep, T, F, N, "ci8")
+        a.copy_(torch.from_numpy(ga.view(np.uint8).reshape(-1)))
+        b.copy_(torch.from_numpy(gb.view(np.uint8).reshape(-1)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        want = oracle.xengine_int(ga, "ci8", T, F, N) + oracle.xengine_int(gb, "ci8", T, F, N)
+        assert np.array_equal(packed_vis(acc, F, N), want), rep
+    plan.close()
+
+
 def test_ci4_long_integration_split_launches():
     # more samples than one launch sums in its int32 registers (65535)
     import torch
@@ -171,6 +245,37 @@ def test_streaming_704_inputs_full_size():
     # exact identity on every channel
     re, im = oracle.unpack_ci4(raw)
     assert freivalds_check(got, re, im, seed=3)
+
+
+def test_bench_ring_stream_704():
+    """The benchmarked step itself: 100 gulps of 704 inputs x 192 channels x
+    1000 ci4 samples stream through a 4-slot input ring; gulp g is correlated
+    with BFX_ACC_OVERWRITE into slot g % 4 of a 4-slot visibility ring and
+    handed over by dump.  After the step every visibility slot holds the
+    integration of its input slot (gulps 96..99): each is checked on all 192
+    channels through the exact Freivalds identity and element by element on
+    two channels against the oracle."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    T, F, N, NG, NS = 1000, 192, 704, 100, 4
+    banner(f"xengine ci4 bench ring stream: {NG} gulps, {NS} slots, T={T} F={F} N={N}")
+    gulps = [synth.voltages(2, T, F, N, "ci4", 2.5, 7, gulp=k) for k in range(NS)]
+    plan = bfx.bfx_xengine_create(N, F, "ci4")
+    ring = [to_dev(g) for g in gulps]
+    vis = [bfx.visibilities_buffer(plan) for _ in range(NS)]
+    for g in range(NG):
+        bfx.bfx_xengine_accumulate(plan, ring[g % NS], T, vis[g % NS], overwrite=True)
+        bfx.bfx_xengine_dump(plan, vis[g % NS], None, None)
+    torch.cuda.synchronize()
+    for k in range(NS):
+        got = packed_vis(vis[k], F, N)
+        for f in ((k * 37) % F, F - 1 - k):
+            want = oracle.xengine_int(gulps[k], "ci4", T, F, N, chans=(f, 1))
+            assert np.array_equal(got[f], want[0]), (k, f)
+        re, im = oracle.unpack_ci4(gulps[k])
+        assert freivalds_check(got, re, im, seed=20 + k), k
+        del got, re, im
+    plan.close()
 
 
 @pytest.mark.parametrize("dtype,T", [("ci8", 96), ("ci8", 256), ("ci8", 320), ("ci4", 512),

@@ -249,6 +249,13 @@ def test_xengine_freivalds_identity_on_oracle():
     bad = out.copy()
     bad[1, 7, 1] += 1
     assert not freivalds_check(bad, re, im, seed=1)
+    # large vectors push the a priori bound past 2^53: the int64 path
+    big = synth.extreme_voltages(22, 512, 2, 32, "ci8")
+    vb = oracle.xengine_int(big, "ci8", 512, 2, 32)
+    bre, bim = oracle.unpack_ci8(big)
+    assert freivalds_check(vb, bre, bim, seed=2, rmax=1 << 24)
+    vb[1, 100, 0] -= 1
+    assert not freivalds_check(vb, bre, bim, seed=2, rmax=1 << 24)
 
 
 def test_xengine_f64_matches_int_on_integer_data():
