@@ -191,6 +191,31 @@ int32_t bfx_tune_cache_lookup(const char *path, const char *arch, const char *dt
 bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t ntime, void *d_acc,
                                   uint32_t flags, bfx_stream stream);
 
+/* Batched correlation for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results as a batched plan built from
+ * (nsub, ninput, nchan, in) followed by bfx_xengine_accumulate with
+ * BFX_ACC_OVERWRITE, but with no plan.  The subarray table and work list
+ * are built on the device, per call, in a fixed scratch array in the
+ * library's device memory (about 0.5 MiB on each device it runs on, held
+ * until the process ends); nothing is allocated or freed.
+ *   nsub      1 .. 16 subarrays (ninput[k] a positive multiple of 4 <= 8192,
+ *             nchan[k] in [1, 65536]); at most 65536 work-list entries in all
+ *             (BFX_ENOTSUP beyond: use a batched plan);
+ *   in        BFX_CI4 or BFX_CI8;
+ *   d_in      device input arena laid out as for bfx_xengine_create_batched;
+ *   ntime     1 .. bfx_xengine_max_ntime(in) samples;
+ *   d_acc     device visibility arena (same layout and size as the plan's);
+ *   flags     must be BFX_ACC_OVERWRITE (no integration state is kept
+ *             between calls; BFX_ENOTSUP otherwise).
+ * Every call on one device uses that device's one scratch array: calls that
+ * overlap on one device (other streams, other host threads) race, and each
+ * call leaves its work list there for the next to overwrite.  Argument errors
+ * are returned before anything is enqueued.                                 */
+bfx_status bfx_xengine_accumulate_batched_noalloc(int32_t nsub, const int32_t *ninput, const int32_t *nchan,
+                                                  bfx_dtype in, const void *d_in, int64_t ntime, void *d_acc,
+                                                  uint32_t flags, bfx_stream stream);
+
 /* Hand over an integration (Sec. 4.1 accumulate block).
  *   d_acc    device visibility buffer filled by accumulate;
  *   d_out    device, may be NULL or == d_acc (no copy); otherwise the

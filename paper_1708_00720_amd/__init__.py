@@ -64,6 +64,8 @@ _SIGS = {
     "bfx_xengine_dump": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "bfx_fengine": (_st, [_vp, _i32, _i32, _i64, _vp, _vp, ctypes.c_int, _vp]),
     "bfx_beamform_detect": (_st, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "bfx_xengine_accumulate_batched_noalloc": (_st, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                                     ctypes.c_int, _vp, _i64, _vp, _u32, _vp]),
     "bfx_beamform_ci4": (_st, [_vp, _vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
     "bfx_probe_mfma": (_st, [_i32, _i32, _i32, _vp, _vp]),
     "bfx_probe_mfma_ops": (_i64, [_i32, _i32, _i32]),
@@ -241,6 +243,15 @@ def bfx_beamform_detect(d_x, d_w, ninput: int, nchan: int, nbeam: int, ntime: in
                         d_out, stream=None):
     _check(_lib.bfx_beamform_detect(_addr(d_x), _addr(d_w), ninput, nchan, nbeam, ntime, navg,
                                     _addr(d_out), _stream(stream)))
+
+
+def bfx_xengine_accumulate_batched_noalloc(ninputs, nchans, dtype, d_in, ntime: int, d_acc,
+                                           stream=None, flags: int = BFX_ACC_OVERWRITE):
+    n = len(ninputs)
+    a = (_i32 * n)(*ninputs)
+    b = (_i32 * n)(*nchans)
+    _check(_lib.bfx_xengine_accumulate_batched_noalloc(n, a, b, _dtype(dtype), _addr(d_in), ntime,
+                                                       _addr(d_acc), flags, _stream(stream)))
 
 
 def bfx_beamform_ci4(d_x, d_w, d_scale, ninput: int, nchan: int, nbeam: int, ntime: int, navg: int,
