@@ -293,6 +293,29 @@ def row_beamform(reps, x=None):
     return r
 
 
+def row_tengine(reps):
+    """T-engine: 256 inputs, 128 frames of 4096-channel ci8 spectra (rounded
+    Gaussian sigma 8), the whole band back to 4096 samples per frame, mixer
+    1/3 channel, 4+4 output."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    S, F, N, NFFT = 128, 4096, 256, 4096
+    g = torch.Generator(device="cuda").manual_seed(12)
+    x = torch.clamp(torch.round(8.0 * torch.randn(S * F * N * 2, device="cuda", generator=g)),
+                    -127, 127).to(torch.int8)
+    out = torch.empty(S * NFFT * N, dtype=torch.uint8, device="cuda")
+    avg, med, _ = time_launches(lambda: bfx.bfx_tengine(x, F, N, S, 0, NFFT, 1, 3 * NFFT, 16.0, out, out="ci4"),
+                                reps)
+    nbytes = S * NFFT * N * 2 + S * NFFT * N
+    flops = int(5 * NFFT * 12) * S * N  # 5 N log2 N per complex transform
+    r = _row("tengine_kernel<ci4>", "256 inputs x 128 frames x 4096-channel band -> 4+4 time series",
+             avg, med, flops, "flops", round(PEAK_FP32_UNPACKED_TFLOPS, 1), "TFLOP/s", "alu", nbytes,
+             {"hbm_frac_algorithmic": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+              "msamples_per_s": round(S * NFFT * N / (avg * 1e-3) / 1e6, 1)})
+    del x, out
+    return r
+
+
 def row_beamform_ci4(reps):
     """Integer beamformer on ci4: 512 inputs, 2048 channels, 1024 samples,
     32 beams of int8 quantized unit-modulus weights, navg 16."""
@@ -386,7 +409,8 @@ def main():
     ap.add_argument("--row-reps", type=int, default=20)
     ap.add_argument("--graph-replays", type=int, default=60,
                     help="replays of the captured 4-gulp ring cycle (timed one by one)")
-    ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "beamform_ci4", "batched"],
+    ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "beamform_ci4", "tengine",
+                                           "batched"],
                     help="only time one row (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -420,7 +444,7 @@ def main():
         return
     if args.only_row:
         fn = {"fengine": row_fengine, "xf16": lambda r: row_xengine_f16(r)[0],
-              "beamform": row_beamform, "beamform_ci4": row_beamform_ci4,
+              "beamform": row_beamform, "beamform_ci4": row_beamform_ci4, "tengine": row_tengine,
               "batched": row_batched}[args.only_row]
         print(json.dumps(fn(args.row_reps)), flush=True)
         return
@@ -539,6 +563,8 @@ def main():
         print("[bench] row: beamformer", file=sys.stderr, flush=True)
         rows["beamform"] = row_beamform(args.row_reps, x16)
         del x16
+        print("[bench] row: T-engine", file=sys.stderr, flush=True)
+        rows["tengine"] = row_tengine(args.row_reps)
         print("[bench] row: ci4 beamformer", file=sys.stderr, flush=True)
         rows["beamform_ci4"] = row_beamform_ci4(args.row_reps)
         print("[bench] row: batched", file=sys.stderr, flush=True)

@@ -268,6 +268,35 @@ bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput,
                                bfx_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* T-engine: channelized spectra back to complex voltages (Sec. 6: the TBN
+ * pipeline's T-engine -- convert to floating point, reduce the bandwidth,
+ * shift along the channel axis, inverse transform, complex mixer for
+ * sub-channel tuning, quantize to 8+8 -- and the DRX T-engine, whose inverse
+ * transform runs on the GPU and whose output is quantized to 4+4).
+ *   d_in     device ci8 spectra [nspec][nchan][ninput] (layout above);
+ *   chan0    first channel of the band, chan0 + nfft <= nchan;
+ *   nfft     band width in channels = output samples per frame, a power of
+ *            two in [64, 8192]; ninput positive and even (this build
+ *            transforms nfft = 4096 with ninput a multiple of 8 and returns
+ *            BFX_ENOTSUP for the other valid shapes);
+ *   mix_num, mix_den  mixer frequency mix_num / mix_den cycles per output
+ *            sample (0 <= mix_num, 1 <= mix_den <= 2^31-1);
+ *   d_out    device [nspec*nfft][ninput] samples of `out`: BFX_CI8 (real byte
+ *            first) or BFX_CI4 (real nibble high), 16-byte aligned.
+ * With X_k = d_in[s][chan0 + k][i] and t = s*nfft + n:
+ *   z[n]  = (1/nfft) sum_{k<nfft} X_k exp(+2 pi i (k - nfft/2) n / nfft)
+ *           (the band centre chan0 + nfft/2 maps to zero frequency),
+ *   z'[n] = z[n] exp(+2 pi i ((mix_num * t) mod mix_den) / mix_den),
+ *   q     = clamp(round_half_even(scale * z'), -L, L) for the real and
+ *           imaginary parts, L = 127 (ci8) or 7 (ci4; -8 is never written).
+ * Computed in binary32 (the mixer phase index is exact integer arithmetic);
+ * a code may differ by one from the exact result where scale * z' lies within
+ * the binary32 error of a half-integer.                                      */
+bfx_status bfx_tengine(const int8_t *d_in, int32_t nchan, int32_t ninput, int64_t nspec, int32_t chan0,
+                       int32_t nfft, int64_t mix_num, int64_t mix_den, float scale, void *d_out, bfx_dtype out,
+                       bfx_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Phase-and-sum beamformer on 4+4-bit voltages with integer weights (Sec. 6:
  * the DRX pipeline's GPU beamformer consumes the 4+4 complex samples
  * directly), square-law detection and integration (Sec. 4.1 detect and

@@ -66,6 +66,7 @@ _SIGS = {
     "bfx_beamform_detect": (_st, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
     "bfx_xengine_accumulate_batched_noalloc": (_st, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                                      ctypes.c_int, _vp, _i64, _vp, _u32, _vp]),
+    "bfx_tengine": (_st, [_vp, _i32, _i32, _i64, _i32, _i32, _i64, _i64, ctypes.c_float, _vp, ctypes.c_int, _vp]),
     "bfx_beamform_ci4": (_st, [_vp, _vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
     "bfx_probe_mfma": (_st, [_i32, _i32, _i32, _vp, _vp]),
     "bfx_probe_mfma_ops": (_i64, [_i32, _i32, _i32]),
@@ -252,6 +253,12 @@ def bfx_xengine_accumulate_batched_noalloc(ninputs, nchans, dtype, d_in, ntime: 
     b = (_i32 * n)(*nchans)
     _check(_lib.bfx_xengine_accumulate_batched_noalloc(n, a, b, _dtype(dtype), _addr(d_in), ntime,
                                                        _addr(d_acc), flags, _stream(stream)))
+
+
+def bfx_tengine(d_in, nchan: int, ninput: int, nspec: int, chan0: int, nfft: int, mix_num: int,
+                mix_den: int, scale: float, d_out, out="ci4", stream=None):
+    _check(_lib.bfx_tengine(_addr(d_in), nchan, ninput, nspec, chan0, nfft, mix_num, mix_den, scale,
+                            _addr(d_out), _dtype(out), _stream(stream)))
 
 
 def bfx_beamform_ci4(d_x, d_w, d_scale, ninput: int, nchan: int, nbeam: int, ntime: int, navg: int,

@@ -49,6 +49,10 @@ hipError_t launch_beamform_ci4(const void *x, const int8_t *w, const float *scal
                                int32_t nchan, int32_t nbeam, int64_t ntime, int32_t navg, float *out,
                                hipStream_t s);
 bool beamform_ci4_supported(int32_t navg);
+hipError_t launch_tengine(const int8_t *in, int32_t nchan, int32_t ninput, int64_t nspec, int32_t chan0,
+                          int32_t nfft, int64_t mix_num, int64_t mix_den, float scale, void *out, bool ci4,
+                          hipStream_t s);
+bool tengine_supported(int32_t ninput, int32_t nfft);
 int64_t beamform_ci4_units(int32_t nchan, int32_t nbeam, int64_t ntime);
 
 }  // namespace bfx
@@ -639,6 +643,36 @@ bfx_status bfx_beamform_detect(const void *d_x, const void *d_w, int32_t ninput,
     hipError_t e = launch_beamform(d_x, d_w, ninput, nchan, nbeam, ntime, navg, d_out,
                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "beamformer launch");
+    return BFX_OK;
+}
+
+bfx_status bfx_tengine(const int8_t *d_in, int32_t nchan, int32_t ninput, int64_t nspec, int32_t chan0,
+                       int32_t nfft, int64_t mix_num, int64_t mix_den, float scale, void *d_out, bfx_dtype out,
+                       bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!d_in || !d_out) return fail(BFX_EINVAL, "d_in / d_out is NULL");
+    if (!aligned16(d_in) || !aligned16(d_out))
+        return fail(BFX_EINVAL, "d_in / d_out must be 16-byte aligned");
+    if (out != BFX_CI8 && out != BFX_CI4) return fail(BFX_EINVAL, "output dtype must be BFX_CI8 or BFX_CI4");
+    if (nfft < 64 || nfft > 8192 || (nfft & (nfft - 1)))
+        return fail(BFX_EINVAL, "nfft=%d must be a power of two in [64, 8192]", nfft);
+    if (ninput <= 0 || (ninput & 1) || ninput > 65536)
+        return fail(BFX_EINVAL, "ninput=%d must be positive and even", ninput);
+    if (nchan <= 0 || nchan > 65536 || chan0 < 0 || (int64_t)chan0 + nfft > nchan)
+        return fail(BFX_EINVAL, "channels chan0=%d .. chan0+nfft-1 must lie inside nchan=%d", chan0, nchan);
+    if (nspec <= 0 || nspec > ((int64_t)1 << 28))
+        return fail(BFX_EINVAL, "nspec=%lld out of range", (long long)nspec);
+    if (mix_den <= 0 || mix_den > 2147483647LL || mix_num < 0)
+        return fail(BFX_EINVAL, "mix_den=%lld must be in [1, 2^31-1] and mix_num=%lld non-negative",
+                    (long long)mix_den, (long long)mix_num);
+    if (!(scale == scale) || scale > 3.4e38f || scale < -3.4e38f)
+        return fail(BFX_EINVAL, "scale must be finite");
+    if (!tengine_supported(ninput, nfft))
+        return fail(BFX_ENOTSUP, "this build transforms nfft=4096 with ninput a multiple of 8 "
+                                 "(got nfft=%d, ninput=%d)", nfft, ninput);
+    hipError_t e = launch_tengine(d_in, nchan, ninput, nspec, chan0, nfft, mix_num, mix_den, scale, d_out,
+                                  out == BFX_CI4, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "T-engine launch");
     return BFX_OK;
 }
 

@@ -35,6 +35,7 @@
 #include <mutex>
 
 #include "bfx_internal.h"
+#include "fft16.h"
 
 namespace bfx {
 namespace {
@@ -49,61 +50,6 @@ constexpr int kFftBytes = kFftElems * 8;            // 34 KiB
 constexpr int kLdsBytes = 2 * kFftBytes;            // ping-pong; two workgroups per CU
 
 __device__ float2 g_twiddle[kN];  // exp(-2 pi i m / 4096), m = 0..4095
-
-__device__ __forceinline__ int pad(int idx) { return idx + (idx >> 4); }
-
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return float2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-
-// forward radix-4 DFT in place on (a0, a1, a2, a3)
-__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
-    const float2 b0{a0.x + a2.x, a0.y + a2.y}, b1{a0.x - a2.x, a0.y - a2.y};
-    const float2 b2{a1.x + a3.x, a1.y + a3.y}, b3{a1.x - a3.x, a1.y - a3.y};
-    a0 = float2{b0.x + b2.x, b0.y + b2.y};
-    a2 = float2{b0.x - b2.x, b0.y - b2.y};
-    a1 = float2{b1.x + b3.y, b1.y - b3.x};  // b1 - i b3
-    a3 = float2{b1.x - b3.y, b1.y + b3.x};  // b1 + i b3
-}
-
-// forward 16-point DFT in registers, natural order in and out:
-// n = 4 n1 + n2, k = k1 + 4 k2,
-// X[k1 + 4 k2] = sum_n2 W4^(n2 k2) W16^(n2 k1) sum_n1 v[4 n1 + n2] W4^(n1 k1).
-__device__ __forceinline__ void dft16(float2 (&v)[16]) {
-    // W16^m = exp(-2 pi i m / 16), m = 0..9 (the products n2 * k1 needed)
-    constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
-    constexpr float c2 = 0.70710678118654752440f;
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
-    // v[n2 + 4 k1] now holds T[n2][k1]; apply W16^(n2 k1)
-    const float2 w1{c1, -s1}, w2{c2, -c2}, w3{s1, -c1}, w4{0.0f, -1.0f}, w6{-c2, -c2},
-        w9{-c1, s1};
-    v[1 + 4] = cmul(v[1 + 4], w1);
-    v[1 + 8] = cmul(v[1 + 8], w2);
-    v[1 + 12] = cmul(v[1 + 12], w3);
-    v[2 + 4] = cmul(v[2 + 4], w2);
-    v[2 + 8] = cmul(v[2 + 8], w4);
-    v[2 + 12] = cmul(v[2 + 12], w6);
-    v[3 + 4] = cmul(v[3 + 4], w3);
-    v[3 + 8] = cmul(v[3 + 8], w6);
-    v[3 + 12] = cmul(v[3 + 12], w9);
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
-    // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4x4 index to natural order
-    float2 t[16];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = t[k];
-}
-
-__device__ __forceinline__ void block_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 __device__ __forceinline__ int8_t requant(float v, float s) {
     float r = rintf(s * v);  // round half to even

@@ -166,3 +166,21 @@ def test_beamform_ci4_argument_errors(kw, code):
         bfx.bfx_beamform_ci4(FAKE, FAKE, FAKE, args["ninput"], args["nchan"], args["nbeam"],
                              args["ntime"], args["navg"], FAKE, stream=0)
     assert ei.value.status == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nfft=100), bfx.BFX_EINVAL), (dict(nfft=32), bfx.BFX_EINVAL), (dict(ninput=3), bfx.BFX_EINVAL),
+    (dict(chan0=1), bfx.BFX_EINVAL), (dict(chan0=-1), bfx.BFX_EINVAL), (dict(nspec=0), bfx.BFX_EINVAL),
+    (dict(mix_den=0), bfx.BFX_EINVAL), (dict(mix_num=-1), bfx.BFX_EINVAL),
+    (dict(mix_den=1 << 31), bfx.BFX_EINVAL), (dict(out="cf32"), bfx.BFX_EINVAL),
+    (dict(scale=float("nan")), bfx.BFX_EINVAL), (dict(nfft=1024, nchan=1024), bfx.BFX_ENOTSUP),
+    (dict(ninput=12), bfx.BFX_ENOTSUP),
+])
+def test_tengine_argument_errors(kw, code):
+    args = dict(nchan=4096, ninput=16, nspec=2, chan0=0, nfft=4096, mix_num=1, mix_den=3, scale=1.0,
+                out="ci4")
+    args.update(kw)
+    with pytest.raises(bfx.BfxError) as ei:
+        bfx.bfx_tengine(FAKE, args["nchan"], args["ninput"], args["nspec"], args["chan0"], args["nfft"],
+                        args["mix_num"], args["mix_den"], args["scale"], FAKE, out=args["out"], stream=0)
+    assert ei.value.status == code

@@ -1,0 +1,101 @@
+"""GPU parity of the T-engine (bfx_tengine: band selection, channel shift,
+inverse transform, complex mixer, 8+8 / 4+4 quantization) against the oracle.
+
+The GPU computes in binary32 and the oracle in double, so a code may round the
+other way only where scale * z' lies within the binary32 error of a
+half-integer.  The window is set a priori: the inverse transform's normwise
+error 8 log2(N) u ||X||_2 / sqrt(N) (X the band of that frame and input), the
+mixer's phase and product rounding 25 u |z'|, and the scale product's own
+rounding u |scale z'|, all times scale.  Every other code must be equal, and
+flagged codes may differ by one at most.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import banner, to_dev
+
+pytestmark = pytest.mark.gpu
+
+NFFT = 4096
+U32 = 2.0 ** -24
+
+
+def _run(x, nchan, ninput, nspec, chan0, mix_num, mix_den, scale, out):
+    import torch
+    import paper_1708_00720_amd as bfx
+    per = 2 if out == "ci8" else 1
+    d_out = torch.full((nspec * NFFT * ninput * per,), 0x55, dtype=torch.uint8, device="cuda")
+    bfx.bfx_tengine(to_dev(x), nchan, ninput, nspec, chan0, NFFT, mix_num, mix_den, scale, d_out, out=out)
+    torch.cuda.synchronize()
+    h = d_out.cpu().numpy()
+    if out == "ci8":
+        q = h.view(np.int8).reshape(nspec * NFFT, ninput, 2).astype(np.int32)
+        return q[..., 0], q[..., 1]
+    re, im = oracle.unpack_ci4(h.reshape(nspec * NFFT, ninput))
+    return re, im
+
+
+def _check(x, gre, gim, chan0, mix_num, mix_den, scale, out, frames, inputs):
+    """Compare the GPU codes of (frames x inputs) with the oracle's.  The
+    oracle runs on each listed frame alone, which gives its mixer the time
+    index n instead of s * nfft + n: the caller lists frames s with
+    mix_num * s * nfft = 0 (mod mix_den), where the two phases agree."""
+    nflag = ndiff = total = 0
+    for s in frames:
+        assert (mix_num * s * NFFT) % mix_den == 0
+        sub = np.ascontiguousarray(x[s:s + 1][:, :, inputs])
+        q, z = oracle.tengine(sub, chan0, NFFT, mix_num, mix_den, scale,
+                              out_bits=8 if out == "ci8" else 4, want_z=True)
+        band = sub[0, chan0:chan0 + NFFT].astype(np.float64)        # [nfft][n][2]
+        xn = np.sqrt((band ** 2).sum(axis=(0, 2)))                   # ||X||_2 per input
+        fft_err = 8 * 12 * U32 * xn / np.sqrt(NFFT)                  # [n]
+        zs = scale * z                                               # [nfft][n][2]
+        win = scale * (fft_err[None, :, None] + 25 * U32 * np.hypot(z[..., 0], z[..., 1])[..., None]) \
+            + 2 * U32 * np.abs(zs)
+        near = np.abs(np.abs(zs - np.floor(zs)) - 0.5) < win
+        g = np.stack([gre[s * NFFT:(s + 1) * NFFT][:, inputs], gim[s * NFFT:(s + 1) * NFFT][:, inputs]], -1)
+        d = g - q
+        bad = (d != 0) & ~near
+        assert not bad.any(), (s, np.argwhere(bad)[:5])
+        assert np.all(np.abs(d) <= 1)
+        nflag += int(near.sum())
+        ndiff += int((d != 0).sum())
+        total += d.size
+    return total, nflag, ndiff
+
+
+@pytest.mark.parametrize("out,scale", [("ci8", 100.0), ("ci4", 6.0), ("ci8", 3.0), ("ci4", 0.7)])
+def test_extreme_codes_small(out, scale):
+    """Uniform codes over the whole int8 range (-128 included), a band inside
+    a wider channel axis, a mixer of 5/4 channel (period 4 frames), five
+    frames checked at frames 0 and 4; the large scales saturate many
+    outputs."""
+    nspec, nchan, ninput, chan0 = 5, NFFT + 40, 16, 40
+    mix_num, mix_den = 5, 4 * NFFT
+    banner(f"tengine {out} extremes scale={scale}")
+    x = synth.extreme_voltages(77, nspec, nchan, ninput, "ci8")
+    gre, gim = _run(x, nchan, ninput, nspec, chan0, mix_num, mix_den, scale, out)
+    total, nflag, ndiff = _check(x, gre, gim, chan0, mix_num, mix_den, scale, out, (0, 4),
+                                 list(range(ninput)))
+    lim = 127 if out == "ci8" else 7
+    assert gre.min() >= -lim and gim.min() >= -lim
+    assert gre.max() <= lim and gim.max() <= lim
+    print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one; "
+          f"{int((np.abs(gre) == lim).sum())} saturated real parts")
+
+
+def test_workload_sampled():
+    """The benchmarked shape: 256 inputs, 128 frames of 4096-channel ci8
+    spectra (rounded Gaussian sigma 8), the whole 4096-channel band, mixer 1/3
+    channel (period 3 frames), 4+4 output; frames 0, 3 and 126 on 16 inputs
+    each."""
+    nspec, nchan, ninput, chan0 = 128, NFFT, 256, 0
+    mix_num, mix_den, scale = 1, 3 * NFFT, 16.0
+    banner("tengine ci4 bench shape: 256 inputs, 128 frames")
+    x = synth.voltages(12, nspec, nchan, ninput, "ci8", 8.0, 127)
+    gre, gim = _run(x, nchan, ninput, nspec, chan0, mix_num, mix_den, scale, "ci4")
+    inputs = [0, 1, 7, 8, 100, 128, 200, 255, 31, 32, 63, 64, 65, 129, 190, 254]
+    total, nflag, ndiff = _check(x, gre, gim, chan0, mix_num, mix_den, scale, "ci4", (0, 3, 126), inputs)
+    print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one")
