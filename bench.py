@@ -548,6 +548,28 @@ def main():
         "hbm_GBps_algorithmic": round((gulp_bytes + out_bytes) / (avg_ms * 1e-3) / 1e9, 1),
     }
 
+    # the exact FP8-MFMA variants of the same plan, timed the same way
+    fp8 = None
+    if bfx.bfx_xengine_num_variants(plan) > 2:
+        fp8 = {}
+        for v in (2, 3):
+            bfx.bfx_xengine_set_variant(plan, v)
+            fevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    for _ in range(reps)]
+            for r in range(reps):
+                fevs[r][0].record(stream)
+                lib.bfx_xengine_accumulate(handle, slot_ptrs[r % N_SLOT], N_TIME, acc_ptrs[r % N_SLOT],
+                                           bfx.BFX_ACC_OVERWRITE, s_ptr)
+                fevs[r][1].record(stream)
+            torch.cuda.synchronize()
+            fd = sorted(a.elapsed_time(b) for a, b in fevs)
+            favg = sum(fd) / len(fd)
+            fp8[f"variant_{v}"] = {"avg_launch_us": round(favg * 1e3, 2),
+                                   "tcmac_per_s": round(cmac_per_gulp() / (favg * 1e-3) / 1e12, 2),
+                                   "fp8_frac": round(8.0 * cmac_per_gulp() / (favg * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)}
+        bfx.bfx_xengine_set_variant(plan, variant)
+        roofline["fp8_mfma_variants"] = fp8
+
     graph = graph_replay_timing(gulp, args.graph_replays)
     print("[bench] peak probes", file=sys.stderr, flush=True)
     peaks = measured_peaks()

@@ -142,28 +142,37 @@ int64_t bfx_xengine_nacc(const bfx_xengine *plan);
 /* ------------------------------------------------------------------------ */
 /* Kernel variants and autotuning (the batched persistent launch of the gulp
  * model, Sec. 3.5, tuned per array shape).  A plan runs one of
- * BFX_XENGINE_VARIANTS kernel variants (they differ in how the stage copies
- * into LDS are shared among the waves); every variant computes the same
- * result (integer paths: the same bits).
+ * bfx_xengine_num_variants(plan) <= BFX_XENGINE_VARIANTS kernel variants;
+ * every variant computes the same result (integer paths: the same bits):
+ *   0, 1  the plan's own MFMA type (int8 for ci4/ci8, binary16 for cf16), with
+ *         four or eight waves issuing the stage copies into LDS;
+ *   2, 3  ci4 plans only (not batched): the same on FP8 MFMA -- every 4-bit
+ *         value is exact in e4m3, products and sums are integers below 2^23
+ *         and binary32 accumulates them exactly (Sec. 6: 4+4-bit voltages;
+ *         Sec. 2.2: quantized types down to a few bits).
  *
  * bfx_xengine_autotune times each variant on the plan's shape with `ntime`
  * samples (1 <= ntime <= min(bfx_xengine_max_ntime, 2^20)) on `stream` and
- * keeps the fastest.  It allocates (and frees) one input gulp and one
- * visibility buffer of device memory, waits for the stream, and leaves nacc
- * unchanged.  times_us, if not NULL, receives the best time of each variant
- * (host float[BFX_XENGINE_VARIANTS], microseconds).  If the environment
+ * keeps the fastest.  It allocates (and frees) one input gulp, filled with
+ * seeded pseudo-random samples spread like the workloads' (not a constant),
+ * and one visibility buffer of device memory, waits for the stream, and
+ * leaves nacc unchanged.  times_us, if not NULL, receives the best time of
+ * each variant (host float[BFX_XENGINE_VARIANTS], microseconds; 0 for
+ * variants the plan does not have).  If the environment
  * variable BFX_TUNE_CACHE names a file, the choice is appended to it as one
  * JSON line {"arch", "dtype", "shape", "variant", "us"}, and plans created
  * later for the same (device architecture, dtype, shape) start with the
  * cached variant (the last matching line wins); otherwise plans start with
  * variant 0.  Returns BFX_EINVAL for a bad ntime, BFX_EHIP if a device
  * allocation or launch fails (the plan keeps its variant).               */
-#define BFX_XENGINE_VARIANTS 2
+#define BFX_XENGINE_VARIANTS 4
 bfx_status bfx_xengine_autotune(bfx_xengine *plan, int64_t ntime, float *times_us, bfx_stream stream);
 
-/* The plan's current variant (-1 for NULL), and an explicit choice
- * (BFX_EINVAL outside [0, BFX_XENGINE_VARIANTS)).                          */
+/* The plan's current variant (-1 for NULL), the number of variants it has
+ * (-1 for NULL), and an explicit choice (BFX_EINVAL outside
+ * [0, bfx_xengine_num_variants(plan))).                                     */
 int32_t bfx_xengine_variant(const bfx_xengine *plan);
+int32_t bfx_xengine_num_variants(const bfx_xengine *plan);
 bfx_status bfx_xengine_set_variant(bfx_xengine *plan, int32_t variant);
 
 /* Look up a tune-cache file without a device: the variant cached for

@@ -58,6 +58,7 @@ _SIGS = {
     "bfx_xengine_nacc": (_i64, [_vp]),
     "bfx_xengine_autotune": (_st, [_vp, _i64, ctypes.POINTER(ctypes.c_float), _vp]),
     "bfx_xengine_variant": (_i32, [_vp]),
+    "bfx_xengine_num_variants": (_i32, [_vp]),
     "bfx_xengine_set_variant": (_st, [_vp, _i32]),
     "bfx_tune_cache_lookup": (_i32, [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p]),
     "bfx_xengine_accumulate": (_st, [_vp, _vp, _i64, _vp, _u32, _vp]),
@@ -200,7 +201,7 @@ def bfx_xengine_nacc(plan: Plan) -> int:
     return int(_lib.bfx_xengine_nacc(plan.handle))
 
 
-BFX_XENGINE_VARIANTS = 2
+BFX_XENGINE_VARIANTS = 4
 
 
 def bfx_xengine_autotune(plan: Plan, ntime: int, stream=None):
@@ -213,6 +214,10 @@ def bfx_xengine_autotune(plan: Plan, ntime: int, stream=None):
 
 def bfx_xengine_variant(plan: Plan) -> int:
     return int(_lib.bfx_xengine_variant(plan.handle))
+
+
+def bfx_xengine_num_variants(plan: Plan) -> int:
+    return int(_lib.bfx_xengine_num_variants(plan.handle))
 
 
 def bfx_xengine_set_variant(plan: Plan, variant: int):

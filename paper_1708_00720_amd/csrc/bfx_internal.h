@@ -55,8 +55,12 @@ constexpr int64_t kLaunchMaxTime = 65535;
 // Integer X-engine (ci4 / ci8 -> int32 packed lower triangle) over one
 // contiguous array.  `in` points at time row t0 of a [t][nchan][ninput] gulp,
 // `nt` <= kLaunchMaxTime rows follow.  `overwrite` stores V, else adds.
-// Kernel variants of the X-engines (0: four DMA waves, 1: eight).
-constexpr int kXengineVariants = 2;
+// Kernel variants of the X-engines: 0 and 1 run the plan's own MFMA type
+// with four or eight DMA waves; ci4 plans also have 2 and 3, the same with
+// FP8 MFMA.  Batched plans have variants 0 and 1.
+constexpr int kXengineVariants = 4;
+constexpr int kBatchedVariants = 2;
+int xengine_num_variants(bfx_dtype in, bool batched);
 
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan,
                               int32_t ninput, int32_t *out, bool overwrite, int variant, hipStream_t s);

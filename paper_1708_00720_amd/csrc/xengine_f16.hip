@@ -206,12 +206,13 @@ __global__ __launch_bounds__(F16Consumer::kThreads, 1) void xengine_f16_kernel(S
 
 // Kernel variants a plan chooses between (index = variant).
 typedef void (*F16Kernel)(SingleArray, int, int, int);
-const F16Kernel kF16[kXengineVariants] = {xengine_f16_kernel<4>, xengine_f16_kernel<8>};
+constexpr int kF16Variants = 2;
+const F16Kernel kF16[kF16Variants] = {xengine_f16_kernel<4>, xengine_f16_kernel<8>};
 
 DeviceInit g_init;
 
 hipError_t set_attributes() {
-    for (int v = 0; v < kXengineVariants; ++v) {
+    for (int v = 0; v < kF16Variants; ++v) {
         const hipError_t e = hipFuncSetAttribute((const void *)kF16[v], hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  kLdsBytes);
         if (e != hipSuccess) return e;
@@ -223,7 +224,7 @@ hipError_t set_attributes() {
 
 hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               float *out, bool overwrite, int variant, hipStream_t s) {
-    if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
+    if (variant < 0 || variant >= kF16Variants) return hipErrorInvalidValue;
     int num_cus = 0;
     const hipError_t e = g_init.ensure(set_attributes, &num_cus);
     if (e != hipSuccess) return e;

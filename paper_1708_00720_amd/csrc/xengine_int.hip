@@ -368,6 +368,167 @@ struct IntConsumer {
     }
 };
 
+// ---------------------------------------------------------------------------
+// ci4 on FP8 MFMA (kernel variants 2 and 3 of a ci4 plan).  Every 4-bit
+// two's-complement value v in [-8, 7] is exact in FP8 e4m3, so the four real
+// products run on v_mfma_scale_f32_32x32x64_f8f6f4 (e4m3 operands, unit
+// scales, binary32 accumulation).  Products are integers of magnitude <= 64
+// and a launch sums at most kLaunchMaxTime = 65535 samples, so every partial
+// sum is an integer below 2^23 and binary32 holds it exactly: the result is
+// the same bits as the int8 path.  On this device FP8 runs at the int8 rate
+// and the nibble-to-e4m3 conversion (two byte-table lookups and a sign
+// select) costs more vector work than the int8 split, so these variants are
+// slower; they are the exact narrow-float alternative the autotuner also
+// times.
+//
+// A stage holds 64 time rows = one K step of 64.  Lane l of a 32-input
+// fragment holds input l % 32 at 32 samples of time half l / 32, from four
+// ds_read_b64_tr_b8 (8 rows each); A and B fragments use the same time order,
+// so their K positions pair up.
+using Q8Fmt = RowFmt<1>;
+static_assert(Q8Fmt::kT == 64, "one 64-sample FP8 MFMA step per stage");
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+struct Q8Acc {
+    v16f rr[2], p[2], q[2];
+};
+
+struct Q8Frag {
+    v8i re, im;
+};
+
+__device__ inline int q8_frag_base(int ioff, int lane) {
+    using F = Q8Fmt;
+    const int G = (lane >> 4) & 3;
+    const int k = lane & 15;
+    const int c = (ioff >> 4) + (G & 1);
+    const int t = 32 * (G >> 1) + (k >> 1);
+    return t * F::kRow + 16 * (c ^ F::swz(t)) + 8 * (k & 1);
+}
+
+// e4m3 codes of the low nibbles (two's complement) of the four bytes of n:
+// 0..7 -> 0x00 0x38 0x40 0x44 0x48 0x4A 0x4C 0x4E, -8..-1 -> 0xD0 0xCE 0xCC
+// 0xCA 0xC8 0xC4 0xC0 0xB8 (two 8-entry byte tables, selected by bit 3).
+__device__ __forceinline__ uint32_t e4m3_of_nibbles(uint32_t n) {
+    const uint32_t sel = n & 0x07070707u;
+    const uint32_t pos = perm(0x4E4C4A48u, 0x44403800u, sel);
+    const uint32_t neg = perm(0xB8C0C4C8u, 0xCACCCED0u, sel);
+    const uint32_t m = perm(0xFFFFFFFFu, 0u, ((n >> 1) & 0x04040404u));  // 0xFF where bit 3 is set
+    return (neg & m) | (pos & ~m);
+}
+
+struct Q8Consumer {
+    static constexpr int kWaves = 8;
+    static constexpr int kThreads = 64 * kWaves;
+    typedef Q8Acc Acc;
+    struct Raw {
+        v2i w[3][4];  // fragments a0, a1, b; four transposing reads each
+    };
+    struct Pre {
+        Q8Frag f[3];
+    };
+    struct Bases {
+        int fb[3];
+    };
+    __device__ static __forceinline__ WaveJob job(const Task &tk, int wave, int ninput) {
+        return make_job_half(tk, wave, ninput);
+    }
+    __device__ static __forceinline__ void zero(Acc &acc) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) acc.rr[r] = acc.p[r] = acc.q[r] = v16f{0.0f};
+    }
+    __device__ static __forceinline__ void bind(const WaveJob &job, int lane, Bases &b) {
+        b.fb[0] = q8_frag_base(job.rrow, lane);
+        b.fb[1] = q8_frag_base(job.rrow + 32, lane);
+        b.fb[2] = q8_frag_base(job.crow, lane);
+    }
+    __device__ static __forceinline__ void read(const uint8_t *st, const Bases &b, Raw &raw) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int rd = 0; rd < 4; ++rd)
+                raw.w[f][rd] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                    (lds_v2i *)(st + b.fb[f] + 8 * rd * Q8Fmt::kRow));
+    }
+    __device__ static __forceinline__ Q8Frag split(const v2i (&w)[4]) {
+        Q8Frag fr;
+#pragma unroll
+        for (int rd = 0; rd < 4; ++rd)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t x = (uint32_t)(h ? w[rd].y : w[rd].x);
+                fr.re[2 * rd + h] = (int)e4m3_of_nibbles(x >> 4);
+                fr.im[2 * rd + h] = (int)e4m3_of_nibbles(x);
+            }
+        return fr;
+    }
+    __device__ static __forceinline__ void prep(const Raw &raw, Pre &pre) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) pre.f[f] = split(raw.w[f]);
+    }
+    __device__ static __forceinline__ void mfma_k(int k, const Pre &p, Acc &acc) {
+        const Q8Frag &a0 = p.f[0], &a1 = p.f[1], &b = p.f[2];
+        switch (k) {
+            case 0: acc.rr[0] = mfma8(a0.re, b.re, acc.rr[0]); break;
+            case 1: acc.rr[1] = mfma8(a1.re, b.re, acc.rr[1]); break;
+            case 2: acc.p[0] = mfma8(a0.im, b.re, acc.p[0]); break;
+            case 3: acc.p[1] = mfma8(a1.im, b.re, acc.p[1]); break;
+            case 4: acc.q[0] = mfma8(a0.re, b.im, acc.q[0]); break;
+            case 5: acc.q[1] = mfma8(a1.re, b.im, acc.q[1]); break;
+            case 6: acc.rr[0] = mfma8(a0.im, b.im, acc.rr[0]); break;
+            default: acc.rr[1] = mfma8(a1.im, b.im, acc.rr[1]); break;
+        }
+    }
+    __device__ static __forceinline__ v16f mfma8(const v8i &a, const v8i &b, const v16f &c) {
+        // e4m3 A and B (format 0), scales 2^0 (E8M0 127)
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+    }
+    __device__ static __forceinline__ void head(const Pre &pre, const Raw &, Acc &acc) {
+#pragma unroll
+        for (int k = 0; k < kHead; ++k) mfma_k(k, pre, acc);
+    }
+    __device__ static __forceinline__ void tail(const Pre &pre, const Raw &, const Raw &nraw, Pre &npre,
+                                                Acc &acc) {
+        // the remaining MFMAs, each followed by a share of the next stage's
+        // conversion (48 dwords of e4m3 codes)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) npre.f[f] = split(nraw.w[f]);
+#pragma unroll
+        for (int k = kHead; k < 8; ++k) mfma_k(k, pre, acc);
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+#pragma unroll
+        for (int i = kHead + 1; i < 8; ++i) {
+            __builtin_amdgcn_sched_group_barrier(kSchedValu, 70, 0);
+            __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __device__ static __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc, int lane,
+                                                    int overwrite) {
+        // exact integers in binary32 -> int32, then the integer epilogue
+        uint8_t *obase = (uint8_t *)it.out + (int64_t)j.ochan * it.out_chan_bytes;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (!((j.live >> (2 * r + j.ch)) & 1u)) continue;
+            v16i rr, pp, qq;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                rr[v] = (int)acc.rr[r][v];
+                pp[v] = (int)acc.p[r][v];
+                qq[v] = (int)acc.q[r][v];
+            }
+            store_sub<false>(obase, j.rblk * kBlk + 32 * r, j.cblk * kBlk + 32 * j.ch, rr, pp, qq, lane,
+                             it.ninput, overwrite);
+        }
+    }
+};
+
+template <int DW>
+__global__ __launch_bounds__(Q8Consumer::kThreads, 1) void xengine_q8_kernel(SingleArray w, int nt,
+                                                                 int total_flat, int overwrite) {
+    xe_loop<Q8Fmt, Q8Consumer, DW>(w, nt, total_flat, overwrite);
+}
+
 // The consumer the integer kernels run.
 template <bool CI4>
 using IntKernelConsumer = IntConsumer<CI4>;
@@ -421,25 +582,31 @@ __global__ __launch_bounds__(IntKernelConsumer<CI4>::kThreads, 1) void xengine_b
 // waves that issue the stage DMA.
 typedef void (*SingleKernel)(SingleArray, int, int, int);
 typedef void (*BatchKernel)(BatchArray, int, int, int);
+// ci8 plans: the int8 kernel with four or eight DMA waves; ci4 plans also
+// the FP8 kernel (variants 2, 3).
 const SingleKernel kSingle[2][kXengineVariants] = {
-    {xengine_int_kernel<false, 4>, xengine_int_kernel<false, 8>},
-    {xengine_int_kernel<true, 4>, xengine_int_kernel<true, 8>}};
-const BatchKernel kBatched[2][kXengineVariants] = {
+    {xengine_int_kernel<false, 4>, xengine_int_kernel<false, 8>, nullptr, nullptr},
+    {xengine_int_kernel<true, 4>, xengine_int_kernel<true, 8>, xengine_q8_kernel<4>, xengine_q8_kernel<8>}};
+const BatchKernel kBatched[2][kBatchedVariants] = {
     {xengine_batched_kernel<false, 4>, xengine_batched_kernel<false, 8>},
     {xengine_batched_kernel<true, 4>, xengine_batched_kernel<true, 8>}};
 
 DeviceInit g_init;
 
 hipError_t set_attributes() {
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) {
         for (int v = 0; v < kXengineVariants; ++v) {
-            hipError_t e = hipFuncSetAttribute((const void *)kSingle[c][v],
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-            if (e != hipSuccess) return e;
-            e = hipFuncSetAttribute((const void *)kBatched[c][v], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBytes);
+            if (!kSingle[c][v]) continue;
+            const hipError_t e = hipFuncSetAttribute((const void *)kSingle[c][v],
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
             if (e != hipSuccess) return e;
         }
+        for (int v = 0; v < kBatchedVariants; ++v) {
+            const hipError_t e = hipFuncSetAttribute((const void *)kBatched[c][v],
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            if (e != hipSuccess) return e;
+        }
+    }
     return hipSuccess;
 }
 
@@ -450,9 +617,14 @@ int64_t xengine_items(int32_t ninput, int32_t nchan) {
     return nb == 1 ? ((int64_t)nchan + 3) / 4 : (int64_t)nchan * tri_items(nb);
 }
 
+int xengine_num_variants(bfx_dtype in, bool batched) {
+    if (batched) return kBatchedVariants;
+    return in == BFX_CI4 ? 4 : 2;
+}
+
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan, int32_t ninput,
                               int32_t *out, bool overwrite, int variant, hipStream_t s) {
-    if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
+    if (variant < 0 || variant >= kXengineVariants || !kSingle[ci4][variant]) return hipErrorInvalidValue;
     int num_cus = 0;
     const hipError_t e = g_init.ensure(set_attributes, &num_cus);
     if (e != hipSuccess) return e;
@@ -478,7 +650,7 @@ hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t ncha
 hipError_t launch_xengine_batched(bool ci4, const void *arena, int64_t ntime, int64_t t0,
                                   int64_t nt, const BatchUnit *d_units, const int2 *d_work,
                                   int64_t nwork, void *out, bool overwrite, int variant, hipStream_t s) {
-    if (variant < 0 || variant >= kXengineVariants) return hipErrorInvalidValue;
+    if (variant < 0 || variant >= kBatchedVariants) return hipErrorInvalidValue;
     int num_cus = 0;
     const hipError_t e = g_init.ensure(set_attributes, &num_cus);
     if (e != hipSuccess) return e;

@@ -41,11 +41,13 @@ def test_int_variants_bit_exact(dtype):
     raw = synth.extreme_voltages(77, T, F, N, dtype)
     plan = bfx.bfx_xengine_create(N, F, dtype)
     want = oracle.xengine_int(raw, dtype, T, F, N)
-    outs = _acc_variants(plan, to_dev(raw), T, bfx.BFX_XENGINE_VARIANTS)
+    nv = bfx.bfx_xengine_num_variants(plan)
+    assert nv == (4 if dtype == "ci4" else 2)
+    outs = _acc_variants(plan, to_dev(raw), T, nv)
     for v, o in enumerate(outs):
         assert np.array_equal(packed_vis(torch.from_numpy(o), F, N), want), f"variant {v}"
     # overwrite, then accumulate onto it
-    outs = _acc_variants(plan, to_dev(raw), T, bfx.BFX_XENGINE_VARIANTS, twice=True)
+    outs = _acc_variants(plan, to_dev(raw), T, nv, twice=True)
     for v, o in enumerate(outs):
         assert np.array_equal(packed_vis(torch.from_numpy(o), F, N), 2 * want), f"variant {v} twice"
     plan.close()
@@ -57,7 +59,7 @@ def test_f16_variants_identical():
     banner(f"variants cf16 T={T} F={F} N={N}")
     x = synth.cf16_voltages(5, T, F, N)
     plan = bfx.bfx_xengine_create(N, F, "cf16")
-    outs = _acc_variants(plan, to_dev(x), T, bfx.BFX_XENGINE_VARIANTS)
+    outs = _acc_variants(plan, to_dev(x), T, bfx.bfx_xengine_num_variants(plan))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     plan.close()
@@ -74,7 +76,7 @@ def test_batched_variants_bit_exact():
         g = synth.extreme_voltages(300 + k, T, F, N, "ci8").view(np.uint8).reshape(-1)
         io, _ = bfx.bfx_xengine_sub_offsets(plan, k, T)
         arena[io:io + g.size] = g
-    outs = _acc_variants(plan, to_dev(arena), T, bfx.BFX_XENGINE_VARIANTS)
+    outs = _acc_variants(plan, to_dev(arena), T, bfx.bfx_xengine_num_variants(plan))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     plan.close()
@@ -95,7 +97,7 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch):
     assert bfx.bfx_xengine_nacc(plan) == 64
     times = bfx.bfx_xengine_autotune(plan, T)
     print("variant times (us):", times)
-    assert all(t > 0 for t in times)
+    assert len(times) == 4 and all(t > 0 for t in times)  # int8 and FP8, four or eight DMA waves
     best = bfx.bfx_xengine_variant(plan)
     assert best == int(np.argmin(times))
     assert bfx.bfx_xengine_nacc(plan) == 64  # the tuning runs leave the count alone

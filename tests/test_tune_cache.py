@@ -44,11 +44,13 @@ def test_missing_file_and_null_arguments(tmp_path):
 def test_set_variant_range_checks():
     plan = bfx.bfx_xengine_create(64, 4, "ci8")
     try:
-        assert bfx.bfx_xengine_variant(plan) in range(bfx.BFX_XENGINE_VARIANTS)
-        for v in range(bfx.BFX_XENGINE_VARIANTS):
+        nv = bfx.bfx_xengine_num_variants(plan)
+        assert nv == 2  # ci8: int8 MFMA with four or eight DMA waves
+        assert bfx.bfx_xengine_variant(plan) in range(nv)
+        for v in range(nv):
             bfx.bfx_xengine_set_variant(plan, v)
             assert bfx.bfx_xengine_variant(plan) == v
-        for bad in (-1, bfx.BFX_XENGINE_VARIANTS):
+        for bad in (-1, nv, bfx.BFX_XENGINE_VARIANTS):
             try:
                 bfx.bfx_xengine_set_variant(plan, bad)
             except bfx.BfxError as e:
@@ -58,6 +60,14 @@ def test_set_variant_range_checks():
     finally:
         plan.close()
     assert bfx._lib.bfx_xengine_variant(None) == -1
+    assert bfx._lib.bfx_xengine_num_variants(None) == -1
+    p4 = bfx.bfx_xengine_create(64, 4, "ci4")
+    try:
+        assert bfx.bfx_xengine_num_variants(p4) == 4  # ci4 also has the FP8 variants
+        bfx.bfx_xengine_set_variant(p4, 3)
+        assert bfx.bfx_xengine_variant(p4) == 3
+    finally:
+        p4.close()
 
 
 def test_autotune_rejects_bad_ntime():
