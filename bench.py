@@ -337,7 +337,7 @@ def row_beamform_ci4(reps):
     avg, med, _ = time_launches(lambda: bfx.bfx_beamform_ci4(x, w, scale, N, F, B, T, NAVG, out), reps)
     cmac = B * F * T * N
     nbytes = T * F * N + F * B * N * 2 + out.numel() * 4
-    r = _row("beamform_ci4_kernel<4>", "512 inputs x 2048 channels x 1024 samples ci4, 32 int8 beams, navg 16",
+    r = _row("beamform_ci4_persistent_kernel<4>", "512 inputs x 2048 channels x 1024 samples ci4, 32 int8 beams, navg 16",
              avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
              {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
               "int8_mfma_frac": round(8 * cmac / (avg * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)})

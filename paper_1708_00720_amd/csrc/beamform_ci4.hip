@@ -86,8 +86,17 @@ __device__ inline void dma16(const void *src, uint32_t lds_wave_base) {
                  : "memory", "m0");
 }
 
+// Wait until at most N vector-memory operations of this wave are in flight
+// (gfx9 encoding: vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt at their
+// maxima).
 template <int N>
-__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(N | 0x0F70); }
+__device__ inline void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Wait until this wave's LDS reads have returned (lgkmcnt = 0).
+__device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // Workgroup barrier without a memory fence: the DMA into LDS is ordered by
 // the explicit vmcnt waits, and every LDS read of a stage has returned (its
@@ -272,18 +281,300 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent kernel for up to 512 inputs (the paper's 256 dual-polarisation
+// antennas and below).  All weights of a (channel, 32-beam group) fit in the
+// registers of the waves that use them (8 K steps of 64 inputs), so a work
+// item covers 1024 samples with its weights loaded once, and the LDS ring runs
+// on across items: no pipeline restart between items.
+//
+// Item = (channel, beam group, 1024 samples), walked by a persistent grid of
+// one workgroup per CU (items of one channel on one XCD, as above).  Eight
+// waves: wave w takes M tile w >> 2 (16 beams) and time quarter w & 3, the 256
+// consecutive samples 256 (w & 3) .. of the item, one 16-sample tile per
+// stage.  A stage is 64 time rows (16 per quarter) x 512 bytes (every input of
+// the row), 32 KiB; four stages rotate, three in flight.  The 16-byte chunks
+// of row R sit at chunk ^ (R & 15), so the 16 rows a wave reads per K step
+// fall on distinct bank groups.
+//
+// Weights travel through LDS too, so that their transfer is counted by the
+// same vector-memory waits as the ring: the (32 beams x 512 inputs x 2) bytes
+// of the next item are fetched into a 32 KiB buffer at stage 8 of the current
+// item, counted in with the ring's waits from stage 12 on, and read into
+// registers (de-interleaved) after the MFMAs of the current item's last stage.
+// Beam row b sits at 1 KiB * b with chunk c at c ^ (b & 15), so the 16 beams
+// a wave reads per K step fall on distinct bank groups.
+constexpr int kPWaves = 8;
+constexpr int kPThreads = 64 * kPWaves;
+constexpr int kPRow = 512;                        // LDS bytes per time row
+constexpr int kPStage = 64 * kPRow;               // 32 KiB
+constexpr int kPSlots = 4;
+constexpr int kPWBytes = kBeams * 1024;           // weight buffer, 32 KiB
+constexpr int kPLds = kPSlots * kPStage + kPWBytes;  // 160 KiB
+constexpr int kPDma = kPStage / 1024 / kPWaves;   // 4 DMA instructions per wave and stage
+constexpr int kPWDma = kPWBytes / 1024 / kPWaves;  // 4 per wave for the weights
+constexpr int kPItemT = 1024;                     // samples per item
+constexpr int kPStages = kPItemT / 64;            // 16 stages per item
+constexpr int kPKS = kPRow / 64;                  // K steps of 64 inputs
+constexpr int kPWStage = 8;                       // stage of an item that fetches the next item's weights
+constexpr int kPMaxInput = kPRow;
+
+__device__ const uint4 kZero16 = {0u, 0u, 0u, 0u};
+
+// Item cursor shared by the producer and the consumer side.
+struct PItem {
+    int B;      // flat item id
+    bool valid;
+    Unit u;
+};
+
+__device__ __forceinline__ void pitem_first(PItem &c, int start, int grid, int total, int ntb, int nbg,
+                                            int nchan) {
+    c.B = start;
+    c.valid = false;
+    while (c.B < total && !(c.valid = unit_of(c.B, ntb, nbg, nchan, c.u))) c.B += grid;
+}
+
+__device__ __forceinline__ void pitem_next(PItem &c, int grid, int total, int ntb, int nbg, int nchan) {
+    pitem_first(c, c.B + grid, grid, total, ntb, nbg, nchan);
+}
+
+// This wave's share of stage k of item u: LDS row R = 2 (kPDma wave + j) +
+// lane / 32 holds time T0 + 256 (R >> 4) + 16 k + (R & 15) (clamped to the
+// last sample), its physical chunk lane % 32 the logical chunk
+// (lane % 32) ^ (R & 15); chunks past the row's inputs fetch chunk 0.
+__device__ __forceinline__ void pstage_dma(const uint8_t *x, int64_t rstride, int ninput, int ntime,
+                                           const PItem &it, int k, uint32_t lds_stage, int wave, int lane) {
+    if (!it.valid) {
+#pragma unroll
+        for (int j = 0; j < kPDma; ++j) dma16(&kZero16, lds_stage + 1024 * (kPDma * wave + j));
+        return;
+    }
+    const int64_t T0 = (int64_t)it.u.tb * kPItemT;
+    const uint8_t *xf = x + (int64_t)it.u.f * ninput;
+    const int nck = ninput >> 4;
+#pragma unroll
+    for (int j = 0; j < kPDma; ++j) {
+        const int R = 2 * (kPDma * wave + j) + (lane >> 5);
+        const int c = (lane & 31) ^ (R & 15);
+        const int cc = c < nck ? c : 0;
+        const int64_t t = min(T0 + 256 * (R >> 4) + 16 * k + (R & 15), (int64_t)ntime - 1);
+        dma16(xf + t * rstride + 16 * cc, lds_stage + 1024 * (kPDma * wave + j));
+    }
+}
+
+// This wave's share of the weights of item u: beam rows b = kPWDma wave + j.
+__device__ __forceinline__ void pweights_dma(const int8_t *w, int ninput, int nbeam, const Unit &u,
+                                             uint32_t lds_w, int wave, int lane) {
+    const int nck = ninput >> 3;  // 16-byte chunks of one beam row
+    const int8_t *w0 = w + (int64_t)u.f * nbeam * ninput * 2;
+#pragma unroll
+    for (int j = 0; j < kPWDma; ++j) {
+        const int b = kPWDma * wave + j;
+        const int beam = u.bg * kBeams + b;
+        const int c = lane ^ (b & 15);
+        const bool ok = c < nck && beam < nbeam;
+        const int64_t off = ok ? ((int64_t)beam * ninput * 2 + 16 * c) : 0;
+        dma16(w0 + off, lds_w + 1024 * b);
+    }
+}
+
+template <int LOGNAVG>
+__global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
+    const uint8_t *__restrict__ x, const int8_t *__restrict__ w, const float *__restrict__ scale,
+    int ninput, int nchan, int nbeam, int ntime, int ntb, int nbg, int total, float *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
+    const uint32_t lds_w = lds_base + kPSlots * kPStage;
+    const uint8_t *wbuf = lds + kPSlots * kPStage;
+    const int grid = gridDim.x;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int m = lane & 15;      // A row (beam in the M tile) / B column (sample in the tile)
+    const int q = lane >> 4;      // K group of 16 inputs; output rows 4q .. 4q+3
+    const int mt = wave >> 2;     // M tile
+    const int qw = wave & 3;      // time quarter
+    const int64_t rstride = (int64_t)nchan * ninput;
+    const int nks = ninput >> 6;
+    const int R = 16 * qw + m;    // LDS row of this lane's B fragments
+
+    PItem cit;  // consumer's item
+    pitem_first(cit, blockIdx.x, grid, total, ntb, nbg, nchan);
+    if (!cit.valid) return;
+    PItem pit = cit;  // producer's item
+    int pk = 0;       // producer's stage within pit
+
+    auto produce = [&](uint32_t slot_base) __attribute__((always_inline)) {
+        pstage_dma(x, rstride, ninput, ntime, pit, pk, slot_base, wave, lane);
+        if (pit.valid && ++pk == kPStages) {
+            pk = 0;
+            pitem_next(pit, grid, total, ntb, nbg, nchan);
+        }
+    };
+
+    // prologue: the first item's weights, then stages 0 .. 3
+    pweights_dma(w, ninput, nbeam, cit.u, lds_w, wave, lane);
+#pragma unroll
+    for (int i = 0; i < kPSlots; ++i) produce(lds_base + i * kPStage);
+    wait_vm<3 * kPDma>();  // weights and stage 0
+    block_barrier();
+
+    v4i wre[kPKS], wim[kPKS];
+    auto load_weights = [&]() __attribute__((always_inline)) {
+        const uint8_t *row = wbuf + 1024 * (16 * mt + m);
+#pragma unroll
+        for (int ks = 0; ks < kPKS; ++ks) {
+            v4i a = v4i{0, 0, 0, 0}, b = v4i{0, 0, 0, 0};
+            if (ks < nks) {
+                const int c = 8 * ks + 2 * q;
+                a = *(const v4i *)(row + 16 * (c ^ m));
+                b = *(const v4i *)(row + 16 * ((c + 1) ^ m));
+            }
+            wre[ks] = v4i{(int)__builtin_amdgcn_perm(a[1], a[0], 0x06040200u),
+                          (int)__builtin_amdgcn_perm(a[3], a[2], 0x06040200u),
+                          (int)__builtin_amdgcn_perm(b[1], b[0], 0x06040200u),
+                          (int)__builtin_amdgcn_perm(b[3], b[2], 0x06040200u)};
+            wim[ks] = v4i{(int)__builtin_amdgcn_perm(a[1], a[0], 0x07050301u),
+                          (int)__builtin_amdgcn_perm(a[3], a[2], 0x07050301u),
+                          (int)__builtin_amdgcn_perm(b[1], b[0], 0x07050301u),
+                          (int)__builtin_amdgcn_perm(b[3], b[2], 0x07050301u)};
+        }
+    };
+    auto read_frags = [&](const uint8_t *stage, v4i (&f)[kPKS]) __attribute__((always_inline)) {
+        const uint8_t *row = stage + kPRow * R;
+#pragma unroll
+        for (int ks = 0; ks < kPKS; ++ks)
+            if (ks < nks) f[ks] = *(const v4i *)(row + 16 * ((4 * ks + q) ^ m));
+    };
+
+    // per-item constants of the detection: squared beam scales
+    double sb2[4];
+    auto item_scales = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int beam = cit.u.bg * kBeams + 16 * mt + 4 * q + v;
+            const double sb = (double)(beam < nbeam ? scale[beam] : 0.0f);
+            sb2[v] = sb * sb;
+        }
+    };
+
+    v4i fa[kPKS], fb[kPKS];
+#pragma unroll
+    for (int ks = 0; ks < kPKS; ++ks) fa[ks] = fb[ks] = v4i{0, 0, 0, 0};
+    load_weights();
+    item_scales();
+    read_frags(lds, fa);
+
+    constexpr int L = LOGNAVG < 4 ? LOGNAVG : 4;
+    constexpr int kTilesPerWin = LOGNAVG > 4 ? 1 << (LOGNAVG - 4) : 1;
+    const int nwin = ntime >> LOGNAVG;
+    int64_t part[4] = {0, 0, 0, 0};
+    PItem cnext = cit;  // the consumer's next item
+    pitem_next(cnext, grid, total, ntb, nbg, nchan);
+    int ck = 0;         // consumer's stage within cit
+    unsigned i = 0;     // consumer's stage in the workgroup's sequence
+
+    // One stage: reads of stage i+1 into nxt, MFMAs and detection of stage i
+    // from cur.  Returns whether a stage follows.
+    auto step = [&](v4i (&cur)[kPKS], v4i (&nxt)[kPKS]) __attribute__((always_inline)) {
+        const bool last = ck + 1 == kPStages;
+        const bool more = !last || cnext.valid;
+        if (more) {
+            // Stage i+1 has landed.  Younger than it: two stages of DMA, and
+            // the next item's weights while they were fetched behind it.
+            if (cnext.valid && ck > kPWStage && ck <= kPWStage + 3) wait_vm<3 * kPDma>();
+            else wait_vm<2 * kPDma>();
+            wait_lds();  // every read of stage i has returned: its slot is refilled now
+            block_barrier();
+            produce(lds_base + (i & (kPSlots - 1)) * kPStage);
+            if (ck == kPWStage && cnext.valid) pweights_dma(w, ninput, nbeam, cnext.u, lds_w, wave, lane);
+            read_frags(lds + ((i + 1) & (kPSlots - 1)) * kPStage, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        v4i rr = v4i{0, 0, 0, 0}, ii = rr, ima = rr, imb = rr;
+#pragma unroll
+        for (int ks = 0; ks < kPKS; ++ks) {
+            if (ks < nks) {
+                v4i xr, xi;
+                split_ci4(cur[ks], xr, xi);
+                rr = __builtin_amdgcn_mfma_i32_16x16x64_i8(wre[ks], xr, rr, 0, 0, 0);
+                ii = __builtin_amdgcn_mfma_i32_16x16x64_i8(wim[ks], xi, ii, 0, 0, 0);
+                ima = __builtin_amdgcn_mfma_i32_16x16x64_i8(wre[ks], xi, ima, 0, 0, 0);
+                imb = __builtin_amdgcn_mfma_i32_16x16x64_i8(wim[ks], xr, imb, 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // the next item's weights (in LDS since its stage kPWStage + 4)
+        if (last && more) load_weights();
+        // detect and integrate: lane holds sample T0 + 256 qw + 16 ck + m of
+        // beams bg*32 + 16 mt + 4q + v
+        const int64_t t = (int64_t)cit.u.tb * kPItemT + 256 * qw + 16 * ck + m;
+        const int64_t uwin = t >> LOGNAVG;
+        const bool flush = (ck % kTilesPerWin) == kTilesPerWin - 1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int yr = (rr[v] - ii[v]) >> 4;
+            const int yi = (ima[v] + imb[v]) >> 4;
+            int64_t p = (int64_t)yr * yr + (int64_t)yi * yi;
+            p = group_sum64<L>(p);
+            part[v] += p;
+            if (flush) {
+                const int beam = cit.u.bg * kBeams + 16 * mt + 4 * q + v;
+                if ((m & ((1 << L) - 1)) == 0 && uwin < nwin && beam < nbeam)
+                    out[((int64_t)beam * nchan + cit.u.f) * nwin + uwin] = (float)(sb2[v] * (double)part[v]);
+                part[v] = 0;
+            }
+        }
+        if (last) {
+            cit = cnext;
+            pitem_next(cnext, grid, total, ntb, nbg, nchan);
+            ck = 0;
+            if (more) item_scales();
+        } else {
+            ++ck;
+        }
+        ++i;
+        return more;
+    };
+    while (step(fa, fb) && step(fb, fa)) {
+    }
+    wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
+}
+
 typedef void (*BfKernel)(const uint8_t *, const int8_t *, const float *, int, int, int, int, int, int,
                          float *);
 const BfKernel kKernels[7] = {beamform_ci4_kernel<0>, beamform_ci4_kernel<1>, beamform_ci4_kernel<2>,
                               beamform_ci4_kernel<3>, beamform_ci4_kernel<4>, beamform_ci4_kernel<5>,
                               beamform_ci4_kernel<6>};
+typedef void (*BfPKernel)(const uint8_t *, const int8_t *, const float *, int, int, int, int, int, int, int,
+                          float *);
+const BfPKernel kPKernels[7] = {beamform_ci4_persistent_kernel<0>, beamform_ci4_persistent_kernel<1>,
+                                beamform_ci4_persistent_kernel<2>, beamform_ci4_persistent_kernel<3>,
+                                beamform_ci4_persistent_kernel<4>, beamform_ci4_persistent_kernel<5>,
+                                beamform_ci4_persistent_kernel<6>};
 
 DeviceInit g_init;
+bool g_persistent_ok[kMaxDevices];  // the device gives a workgroup kPLds bytes of LDS
 
 hipError_t set_attributes() {
     for (BfKernel k : kKernels) {
         const hipError_t e =
             hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+    }
+    int dev = 0, lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && optin > lds)
+        lds = optin;
+    g_persistent_ok[dev] = lds >= kPLds;
+    if (!g_persistent_ok[dev]) return hipSuccess;
+    for (BfPKernel k : kPKernels) {
+        e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kPLds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -302,14 +593,30 @@ int64_t beamform_ci4_units(int32_t nchan, int32_t nbeam, int64_t ntime) {
 hipError_t launch_beamform_ci4(const void *x, const int8_t *w, const float *scale, int32_t ninput,
                                int32_t nchan, int32_t nbeam, int64_t ntime, int32_t navg, float *out,
                                hipStream_t s) {
-    const hipError_t e = g_init.ensure(set_attributes, nullptr);
+    int num_cus = 0;
+    const hipError_t e = g_init.ensure(set_attributes, &num_cus);
     if (e != hipSuccess) return e;
+    int dev = 0;
+    const hipError_t ed = hipGetDevice(&dev);
+    if (ed != hipSuccess) return ed;
     int lognavg = 0;
     while ((1 << lognavg) < navg) ++lognavg;
-    const int ntb = (int)((ntime + kTB - 1) / kTB);
     const int nbg = (nbeam + kBeams - 1) / kBeams;
     const int64_t units = beamform_ci4_units(nchan, nbeam, ntime);
     if (units > kMaxWorkgroups256) return hipErrorInvalidConfiguration;
+    if (ninput <= kPMaxInput && g_persistent_ok[dev]) {
+        // items of 1024 samples: never more than the 256-sample units above
+        const int ntb = (int)((ntime + kPItemT - 1) / kPItemT);
+        const int64_t total = ((int64_t)nchan + 7) / 8 * 8 * ntb * nbg;
+        int64_t grid = (int64_t)(num_cus > 0 ? num_cus : 256) / 8 * 8;
+        if (grid < 8) grid = 8;
+        if (grid > total) grid = total;
+        hipLaunchKernelGGL(kPKernels[lognavg], dim3((unsigned)grid), dim3(kPThreads), kPLds, s,
+                           (const uint8_t *)x, w, scale, ninput, nchan, nbeam, (int)ntime, ntb, nbg, (int)total,
+                           out);
+        return hipGetLastError();
+    }
+    const int ntb = (int)((ntime + kTB - 1) / kTB);
     hipLaunchKernelGGL(kKernels[lognavg], dim3((unsigned)units), dim3(kThreads), kLdsBytes, s,
                        (const uint8_t *)x, w, scale, ninput, nchan, nbeam, (int)ntime, ntb, nbg, out);
     return hipGetLastError();

@@ -15,19 +15,33 @@
 // neighbouring input groups meet in one L2.  Two adjacent real inputs a, b
 // form one complex sequence z = x_a + i x_b (two-for-one); the workgroup's
 // 256 lanes transform its 4 pairs one at a time with a radix-16 Stockham FFT
-// (4096 = 16^3, three passes, 16 points per lane in registers, the passes
-// exchanging through two padded LDS buffers in turn, so each exchange needs
-// one barrier), and
+// (4096 = 16^3, three passes, 16 points per lane in registers), and
 //   X_a[k] = (Z[k] + conj Z[-k]) / 2,   X_b[k] = (Z[k] - conj Z[-k]) / (2i).
+//
+// Exchanges.  Passes 1 -> 2 and 2 -> 3 go through two LDS buffers (one
+// barrier each; the buffers alternate so no other barrier is needed).  Every
+// half-wave's accesses of each exchange fall on distinct banks: the first
+// buffer is padded (an additive map, folded into the instructions' offsets),
+// the second XOR-swizzled (no additive map serves its accesses).  The third
+// pass gives each wave a set of butterflies closed under b -> 256 - b, with
+// butterfly b in lane i < 32 and 256 - b in lane i + 32 (wave 0 keeps the
+// self-paired 0 and 128 in lanes 0 and 32).  Butterfly b holds Z[b + 256 m],
+// and Z[-k] for k = b + 256 m is register 15 - m of butterfly 256 - b, so the
+// split needs one v_permlane32_swap per register -- a wavefront shuffle, no
+// LDS and no barrier.  The third pass reads butterflies above 128 in reversed
+// order in a buffer laid out to match (index map piB), so both half-waves read
+// ascending addresses.
+//
 // The samples a lane needs for the first pass (16 rows, the item's 8 inputs)
-// come straight from global memory into registers, fetched one item ahead so
-// that the loads overlap the current item's transforms; the twiddles of the
+// come straight from global memory into registers; the next item's are
+// fetched into the same registers once the last pair has taken them, so the
+// loads overlap that pair's transform.  The twiddles of the
 // lane's second- and third-pass butterflies (which depend only on the lane)
 // are loaded once per workgroup into registers.  A lane's requantized bytes
 // of its 8 channels stay in registers across the 4 pairs and leave as one
-// 16-byte [k][8 inputs] segment per channel.  Twiddles come from a 4096-entry table
-// computed once per device in FP64 on the host from the exact integer phase
-// k n mod 4096, then rounded to binary32.
+// 16-byte [k][8 inputs] segment per channel.  Twiddles come from a 4096-entry
+// table computed once per device in FP64 on the host from the exact integer
+// phase k n mod 4096, then rounded to binary32.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -45,9 +59,27 @@ constexpr int kChan = kN / 2;      // channels kept
 constexpr int kGroup = 8;          // inputs per workgroup
 constexpr int kPairs = kGroup / 2; // complex sequences per workgroup
 constexpr int kThreads = 256;      // lanes of one FFT (4096 / 16 points each)
-constexpr int kFftElems = kN + kN / 16;             // one pad float2 per 16
-constexpr int kFftBytes = kFftElems * 8;            // 34 KiB
-constexpr int kLdsBytes = 2 * kFftBytes;            // ping-pong; two workgroups per CU
+constexpr int kABytes = kPadAElems * 8;             // pass 1 -> 2, padded (pad_a)
+constexpr int kBBytes = kN * 8;                     // pass 2 -> 3, swizzled (swz_b)
+constexpr int kTw2Bytes = 256 * 8;                  // pass-2 twiddles W^(16 r c), r, c < 16
+constexpr int kLdsBytes = kABytes + kBBytes + kTw2Bytes;  // two workgroups per CU
+
+// Buffer A (pass 1 -> 2) uses the additive pad_a (fft16.h).
+// Buffer B (pass 2 -> 3): butterflies above 128 of each 256 block in reversed
+// order (piB), then x ^ (((x >> 8) & 15) << 4): conflict-free for the pass-2
+// writes and for both half-waves' pass-3 reads.
+__device__ __forceinline__ int swz_b(int x) {
+    const int b = x & 255;
+    const int y = (x & ~255) | (b <= 128 ? b : 384 - b);
+    return y ^ (((y >> 8) & 15) << 4);
+}
+// Third-pass butterfly of lane tid (see the header).
+__device__ __forceinline__ int pass3_butterfly(int tid) {
+    const int w = tid >> 6, i = tid & 63;
+    if (i < 32) return 32 * w + i;
+    const int i2 = i - 32;
+    return (w == 0 && i2 == 0) ? 128 : 256 - 32 * w - i2;
+}
 
 __device__ float2 g_twiddle[kN];  // exp(-2 pi i m / 4096), m = 0..4095
 
@@ -67,11 +99,11 @@ __device__ __forceinline__ bool item_of(int B, int ngroup, int nspec, int &s, in
 }
 
 // The 16 first-pass rows (j + 256 r) of this lane for the item's 8 inputs.
-__device__ __forceinline__ void load_samples(uint2 (&x)[16], const int8_t *in, int ninput, int s,
+__device__ __forceinline__ void load_samples(uint64_t (&x)[16], const int8_t *in, int ninput, int s,
                                              int g, int j) {
     const int8_t *src = in + ((int64_t)s * kN + j) * ninput + g * kGroup;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = *(const uint2 *)(src + (int64_t)(256 * r) * ninput);
+    for (int r = 0; r < 16; ++r) x[r] = *(const uint64_t *)(src + (int64_t)(256 * r) * ninput);
 }
 
 template <bool CI8>
@@ -82,7 +114,7 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
     const int tid = threadIdx.x;
     const int j = tid;                     // lane of the FFT
     float2 *buf0 = (float2 *)lds;          // pass 1 -> 2, pass 3 -> split
-    float2 *buf1 = (float2 *)(lds + kFftBytes);  // pass 2 -> 3
+    float2 *buf1 = (float2 *)(lds + kABytes);  // pass 2 -> 3
 
     int B = blockIdx.x, s = 0, g = 0;
     bool valid = false;
@@ -90,86 +122,101 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
     if (!valid) return;
 
     // twiddles of this lane's pass-2 (Ns = 16) and pass-3 (Ns = 256) butterflies
-    float2 tw2[16], tw3[16];
-    {
-        const int m2 = (j & 15) * (kN / 256), m3 = j;
+    const int b3 = pass3_butterfly(j);
+    const bool self0 = b3 == 0, self128 = b3 == 128;  // self-paired butterflies
+    const bool lower = (j & 63) < 32;
+    // pass-3 twiddles in registers; the pass-2 ones (16 distinct sets, by
+    // j % 16) in a small LDS table, published by the first barrier
+    float2 tw3[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            tw2[r] = g_twiddle[(r * m2) & (kN - 1)];
-            tw3[r] = g_twiddle[(r * m3) & (kN - 1)];
-        }
-    }
-    uint2 xs[16];
+    for (int r = 0; r < 16; ++r) tw3[r] = g_twiddle[(r * b3) & (kN - 1)];
+    float2 *tw2 = (float2 *)(lds + kABytes + kBBytes);
+    tw2[j] = g_twiddle[((j >> 4) * (j & 15) * (kN / 256)) & (kN - 1)];  // entry 16 r + c
+    // a row's 8 bytes (the item's 8 inputs); each pair takes the low 16 bits
+    // and shifts them out, so the pair loop never selects by its index
+    uint64_t xs[16];
     load_samples(xs, in, ninput, s, g, j);
 
     while (true) {
-        // next item: its samples are fetched while this one is transformed
+        // next item: its samples are fetched into the registers of this
+        // item's samples once the last pair has taken them (the loads then
+        // overlap that pair's transform)
         int Bn = B + gridDim.x, sn = 0, gn = 0;
         bool nvalid = false;
         while (Bn < total_flat && !(nvalid = item_of(Bn, ngroup, nspec, sn, gn))) Bn += gridDim.x;
-        uint2 xn[16];
-        if (nvalid) load_samples(xn, in, ninput, sn, gn, j);
         const int i0 = g * kGroup;
 
-        uint32_t q[kChan / kThreads][kPairs];  // ci8 bytes (a_re, a_im, b_re, b_im)
-        // Buffers: pass 1 -> A, pass 2 A -> B, pass 3 B -> A, split reads A,
-        // with A and B swapping from pair to pair.  Every write then targets
-        // a buffer whose last reads precede a barrier already passed, so one
-        // barrier per exchange suffices (three per pair).
-#pragma unroll
+        // ci8 bytes (a_re, a_im, b_re, b_im) of each pair, rotated in pair by
+        // pair so that after the last pair q[c] holds pairs 0..3 in order
+        uint4 q[kChan / kThreads];
+        // Buffers: pass 1 -> A, pass 2 A -> B, pass 3 reads B.  The next
+        // pair's pass-1 writes to A follow this pair's barrier after pass 2
+        // (all reads of A done) and its pass-2 writes to B follow the next
+        // pair's first barrier (all pass-3 reads of B done): two barriers per
+        // pair.
+        float2 *A = buf0;
+        float2 *Bf = buf1;
+        // (not unrolled: one pair's registers at a time)
+#pragma unroll 1
         for (int p = 0; p < kPairs; ++p) {
-            float2 *A = (p & 1) ? buf1 : buf0;
-            float2 *Bf = (p & 1) ? buf0 : buf1;
             // pass 1 (Ns = 1): z[n] = x_a[n] + i x_b[n], n = j + 256 r
             float2 v[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint32_t w = p < 2 ? xs[r].x : xs[r].y;  // bytes 2 p, 2 p + 1
-                const uint32_t two = w >> (16 * (p & 1));
+                const uint32_t two = (uint32_t)xs[r];  // bytes 2 p, 2 p + 1 of the row
+                xs[r] >>= 16;
                 v[r] = float2{(float)(int8_t)(two & 0xFF), (float)(int8_t)((two >> 8) & 0xFF)};
             }
+            if (p == kPairs - 1 && nvalid) load_samples(xs, in, ninput, sn, gn, j);
             dft16(v);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) A[pad(16 * j + r)] = v[r];
+            for (int r = 0; r < 16; ++r) A[pad_a(16 * j + r)] = v[r];
             block_barrier();
             // pass 2 (Ns = 16): A -> B
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float2 x = A[pad(j + 256 * r)];
-                v[r] = r == 0 ? x : cmul(x, tw2[r]);
+                const float2 x = A[pad_a(j + 256 * r)];
+                v[r] = r == 0 ? x : cmul(x, tw2[16 * r + (j & 15)]);
             }
             dft16(v);
             {
                 const int base = (j / 16) * 256 + (j & 15);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) Bf[pad(base + r * 16)] = v[r];
+                for (int r = 0; r < 16; ++r) Bf[swz_b(base + r * 16)] = v[r];
             }
             block_barrier();
-            // pass 3 (Ns = 256): B -> A
+            // pass 3 (Ns = 256): butterfly b3, outputs Z[b3 + 256 m] in v[m]
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float2 x = Bf[pad(j + 256 * r)];
+                const float2 x = Bf[swz_b(b3 + 256 * r)];
                 v[r] = r == 0 ? x : cmul(x, tw3[r]);
             }
             dft16(v);
-#pragma unroll
-            for (int r = 0; r < 16; ++r) A[pad(j + r * 256)] = v[r];
-            block_barrier();
-            // two-for-one split for k = j + 256 c, c = 0..7
+            // two-for-one split for k = b3 + 256 m, m = 0..7:
+            // Z[-k] = register 15 - m of butterfly 256 - b3, 32 lanes away
+            // (one v_permlane32_swap per component); butterfly 0 uses its own
+            // register (16 - m) % 16, butterfly 128 its own register 15 - m
 #pragma unroll
             for (int c = 0; c < kChan / kThreads; ++c) {
-                const int k = j + kThreads * c;
-                const float2 z = A[pad(k)];
-                const float2 w = A[pad((kN - k) & (kN - 1))];
+                const int k = b3 + kThreads * c;
+                const float2 z = v[c];
+                const auto sx = __builtin_amdgcn_permlane32_swap(__float_as_int(v[15 - c].x),
+                                                                  __float_as_int(v[15 - c].x), false, false);
+                const auto sy = __builtin_amdgcn_permlane32_swap(__float_as_int(v[15 - c].y),
+                                                                  __float_as_int(v[15 - c].y), false, false);
+                float2 w{__int_as_float(lower ? sx[1] : sx[0]), __int_as_float(lower ? sy[1] : sy[0])};
+                if (self128) w = v[15 - c];
+                if (self0) w = v[(16 - c) & 15];
                 // X_a = (z + conj w)/2, X_b = (z - conj w)/(2i) = -i (z - conj w)/2
                 const float2 xa{0.5f * (z.x + w.x), 0.5f * (z.y - w.y)};
                 const float2 xb{0.5f * (z.y + w.y), -0.5f * (z.x - w.x)};
                 if (CI8) {
                     const float sc = scale[k];
-                    q[c][p] = (uint32_t)(uint8_t)requant(xa.x, sc) |
-                              ((uint32_t)(uint8_t)requant(xa.y, sc) << 8) |
-                              ((uint32_t)(uint8_t)requant(xb.x, sc) << 16) |
-                              ((uint32_t)(uint8_t)requant(xb.y, sc) << 24);
+                    const uint32_t word = (uint32_t)(uint8_t)requant(xa.x, sc) |
+                                          ((uint32_t)(uint8_t)requant(xa.y, sc) << 8) |
+                                          ((uint32_t)(uint8_t)requant(xb.x, sc) << 16) |
+                                          ((uint32_t)(uint8_t)requant(xb.y, sc) << 24);
+                    q[c] = uint4{q[c].y, q[c].z, q[c].w, word};
                 } else {
                     float4 *o = (float4 *)((float *)out +
                                            (((int64_t)s * kChan + k) * ninput + i0 + 2 * p) * 2);
@@ -182,17 +229,14 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
             int8_t *o = (int8_t *)out;
 #pragma unroll
             for (int c = 0; c < kChan / kThreads; ++c) {
-                const int k = j + kThreads * c;
-                *(uint4 *)(o + (((int64_t)s * kChan + k) * ninput + i0) * 2) =
-                    uint4{q[c][0], q[c][1], q[c][2], q[c][3]};
+                const int k = b3 + kThreads * c;
+                *(uint4 *)(o + (((int64_t)s * kChan + k) * ninput + i0) * 2) = q[c];
             }
         }
         if (!nvalid) break;
         B = Bn;
         s = sn;
         g = gn;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) xs[r] = xn[r];
     }
 }
 

@@ -1,13 +1,22 @@
 // Radix-16 building blocks of the FFT kernels (F-engine and T-engine):
 // complex multiply, forward 4- and 16-point DFTs in registers, the padded
-// LDS index of the Stockham exchanges and a fence-free workgroup barrier.
+// LDS indices of the Stockham exchanges and a fence-free workgroup barrier.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace bfx {
 namespace {
 
-__device__ __forceinline__ int pad(int idx) { return idx + (idx >> 4); }
+// Padded float2 index of the 4096-point exchange buffers.  For 32 consecutive
+// lanes j and a fixed r, 8-byte accesses at these indices fall on 64
+// distinct banks; both paddings are additive, so a lane's 16 accesses of an
+// exchange differ by constants and fold into the instructions' offsets.
+//   pad_a: pass-1 writes 16 j + r and the reads j + 256 r that follow;
+//   pad_b: writes (j / 16) 256 + j % 16 + 16 r and the reads j + 256 r.
+constexpr int kPadAElems = 4096 + 4096 / 32;
+constexpr int kPadBElems = 4096 + 3 * (4096 / 64) + 2 * (4096 / 128);
+__device__ __forceinline__ int pad_a(int x) { return x + (x >> 5); }
+__device__ __forceinline__ int pad_b(int x) { return x + 3 * (x >> 6) + 2 * (x >> 7); }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return float2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};

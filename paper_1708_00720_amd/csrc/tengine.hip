@@ -39,8 +39,9 @@ namespace {
 constexpr int kN = 4096;
 constexpr int kGroup = 8;
 constexpr int kThreads = 256;
-constexpr int kFftBytes = (kN + kN / 16) * 8;
-constexpr int kLdsBytes = 2 * kFftBytes;
+constexpr int kABytes = kPadAElems * 8;  // pass 1 -> 2 (pad_a)
+constexpr int kBBytes = kPadBElems * 8;  // pass 2 -> 3 (pad_b)
+constexpr int kLdsBytes = kABytes + kBBytes;
 
 __device__ float2 g_tw[kN];  // exp(-2 pi i m / 4096), m = 0..4095
 
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int j = threadIdx.x;
     float2 *A = (float2 *)lds;
-    float2 *Bf = (float2 *)(lds + kFftBytes);
+    float2 *Bf = (float2 *)(lds + kABytes);
     constexpr float lim = CI4 ? 7.0f : 127.0f;
     constexpr float inv_n = 1.0f / kN;
 
@@ -118,23 +119,23 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
             }
             dft16(v);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) A[pad(16 * j + r)] = v[r];
+            for (int r = 0; r < 16; ++r) A[pad_a(16 * j + r)] = v[r];
             block_barrier();
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float2 x = A[pad(j + 256 * r)];
+                const float2 x = A[pad_a(j + 256 * r)];
                 v[r] = r == 0 ? x : cmul(x, tw2[r]);
             }
             dft16(v);
             {
                 const int base = (j / 16) * 256 + (j & 15);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) Bf[pad(base + r * 16)] = v[r];
+                for (int r = 0; r < 16; ++r) Bf[pad_b(base + r * 16)] = v[r];
             }
             block_barrier();
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float2 x = Bf[pad(j + 256 * r)];
+                const float2 x = Bf[pad_b(j + 256 * r)];
                 v[r] = r == 0 ? x : cmul(x, tw3[r]);
             }
             dft16(v);

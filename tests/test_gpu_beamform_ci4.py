@@ -6,7 +6,11 @@ one conversion P = fl32(fl64(scale^2) * fl64(S)) takes the same rounding
 steps, so every output word must be equal.  Cases: extreme codes (-8 voltages,
 -128 weights) over ragged shapes and every navg, a sum S above 2^53 (where the
 conversion to double rounds), and the full workload (512 inputs, 2048
-channels, 1024 samples, 32 beams, navg 16) on sampled channels.
+channels, 1024 samples, 32 beams, navg 16) on sampled channels.  Up to 512
+inputs the library runs a persistent kernel whose workgroups walk many
+(channel, beam group, 1024-sample) items in turn; beyond that, one workgroup
+per (channel, 256 samples, beam group).  Both are covered, and a ragged case
+with thousands of items checks the item-to-item hand-over.
 """
 import numpy as np
 import pytest
@@ -31,6 +35,7 @@ def _run(x, w, scale, N, F, B, T, navg):
 @pytest.mark.parametrize("N,F,B,T,navg", [
     (64, 1, 1, 16, 16), (64, 3, 5, 48, 1), (128, 2, 32, 256, 2), (192, 5, 33, 320, 4),
     (320, 3, 40, 512, 8), (512, 9, 64, 272, 16), (256, 4, 7, 640, 32), (448, 2, 16, 768, 64),
+    (576, 3, 17, 272, 16), (1024, 2, 33, 512, 64),
 ])
 def test_extreme_codes_ragged(N, F, B, T, navg):
     banner(f"beamform_ci4 extremes N={N} F={F} B={B} T={T} navg={navg}")
@@ -67,5 +72,22 @@ def test_full_size_sampled_channels():
     w, scale = synth.int8_steering_weights(10, F, B, N)
     got = _run(x, w, scale, N, F, B, T, navg)
     for f in (0, 1, 7, 8, 1000, 2047):
+        want = oracle.beamform_ci4(np.ascontiguousarray(x[:, f:f + 1]), w[f:f + 1], scale, navg)
+        assert np.array_equal(got[:, f:f + 1].view(np.uint32), want.view(np.uint32)), f
+
+
+def test_many_items_ragged():
+    """128 inputs, 520 channels, 40 beams (two beam groups, the second
+    partial), 2304 samples (two whole 1024-sample items and a partial one),
+    navg 32: about 3000 items, so every workgroup hands over between items of
+    different channels, beam groups and time blocks.  Sampled channels are
+    checked bit-exact."""
+    N, F, B, T, navg = 128, 520, 40, 2304, 32
+    banner(f"beamform_ci4 many items N={N} F={F} B={B} T={T} navg={navg}")
+    x = synth.extreme_voltages(31, T, F, N, "ci4")
+    w = synth.extreme_int8_weights(32, F, B, N)
+    scale = np.random.default_rng(33).uniform(0.001, 3.0, B).astype(np.float32)
+    got = _run(x, w, scale, N, F, B, T, navg)
+    for f in (0, 1, 7, 8, 255, 256, 263, 511, 512, 519):
         want = oracle.beamform_ci4(np.ascontiguousarray(x[:, f:f + 1]), w[f:f + 1], scale, navg)
         assert np.array_equal(got[:, f:f + 1].view(np.uint32), want.view(np.uint32)), f
