@@ -118,6 +118,14 @@ __device__ inline int64_t swz_xor64(int64_t v) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+template <int K>
+__device__ inline double swz_xor_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = swz_xor<K>((int)(uint32_t)b);
+    const int hi = swz_xor<K>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Sum over aligned groups of 2^L consecutive lanes (L <= 4), in int64.
 template <int L>
 __device__ inline int64_t group_sum64(int64_t p) {
@@ -147,6 +155,31 @@ __device__ __forceinline__ void stage_dma(const uint8_t *xf, int64_t rstride, in
         const int t = min(tu + 64 * (R >> 4) + 16 * s + (R & 15), ntime - 1);
         const int cc = c < cpr ? c : 0;
         dma16(xf + (int64_t)t * rstride + kc + 16 * cc, lds_stage + 1024 * ins);
+    }
+}
+
+// Lane exchange with the lane 32 away (v_permlane32_swap).
+__device__ inline int xor32(int v, int lane) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return lane < 32 ? r[1] : r[0];
+}
+
+__device__ inline double xor32_f64(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = xor32((int)(uint32_t)b, lane);
+    const int hi = xor32((int)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// ci4 bytes 16 re + (im & 15) -> R = 16 re (the high nibble in place) and
+// X' = 16 re + (im + 8) (bit 3 flipped: the low nibble becomes im + 8 in
+// 0..15), both exact int8.  Against weights w, X' gives 16 sum(re w) +
+// sum(im w) + 8 sum(w): the last term is a per-beam constant.
+__device__ __forceinline__ void split_ci4_offset(const v4i raw, v4i &r, v4i &xo) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r[k] = (int)((uint32_t)raw[k] & 0xF0F0F0F0u);
+        xo[k] = (int)((uint32_t)raw[k] ^ 0x08080808u);
     }
 }
 
@@ -297,6 +330,17 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
 // of row R sit at chunk ^ (R & 15), so the 16 rows a wave reads per K step
 // fall on distinct bank groups.
 //
+// The product is taken transposed, D[sample][beam] = X W^T (the operands of
+// v_mfma_i32_16x16x64_i8 have the same lane layout on both sides), so a lane
+// holds four consecutive samples of one beam: windows of up to 4 samples are
+// lane-local, 8 and 16 add the lanes 16 and 32 away, 32 and 64 add
+// consecutive stages.  The nibble split takes two operations per word
+// instead of three: R = 16 re (mask) and X' = 16 re + im + 8 (flip bit 3),
+//   P1 = R Wre, P2 = X' Wre, Q1 = R Wim, Q2 = X' Wim,
+//   Re y = P1/16 - (Q2 - Q1 - 8 S_im),  Im y = Q1/16 + (P2 - P1 - 8 S_re),
+// with S_re, S_im the sums of the beam's weight components over the inputs,
+// computed once per item.  Every term is an exact int32.
+//
 // Weights travel through LDS too, so that their transfer is counted by the
 // same vector-memory waits as the ring: the (32 beams x 512 inputs x 2) bytes
 // of the next item are fetched into a 32 KiB buffer at stage 8 of the current
@@ -318,6 +362,7 @@ constexpr int kPStages = kPItemT / 64;            // 16 stages per item
 constexpr int kPKS = kPRow / 64;                  // K steps of 64 inputs
 constexpr int kPWStage = 8;                       // stage of an item that fetches the next item's weights
 constexpr int kPMaxInput = kPRow;
+static_assert(kPWStage + kPSlots < kPStages, "the next item's weights land before the item's last stage");
 
 __device__ const uint4 kZero16 = {0u, 0u, 0u, 0u};
 
@@ -417,7 +462,7 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
     pweights_dma(w, ninput, nbeam, cit.u, lds_w, wave, lane);
 #pragma unroll
     for (int i = 0; i < kPSlots; ++i) produce(lds_base + i * kPStage);
-    wait_vm<3 * kPDma>();  // weights and stage 0
+    wait_vm<(kPSlots - 1) * kPDma>();  // weights and stage 0
     block_barrier();
 
     v4i wre[kPKS], wim[kPKS];
@@ -448,28 +493,42 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
             if (ks < nks) f[ks] = *(const v4i *)(row + 16 * ((4 * ks + q) ^ m));
     };
 
-    // per-item constants of the detection: squared beam scales
-    double sb2[4];
-    auto item_scales = [&]() __attribute__((always_inline)) {
+    // Per-item constants of this lane's beam (bg*32 + 16 mt + m): its squared
+    // scale, and 8 x the sums of its weights' real and imaginary parts over
+    // all inputs (the offset that X' carries into P2 and Q2).
+    double sb2 = 0.0;
+    int c8re = 0, c8im = 0;
+    auto item_consts = [&]() __attribute__((always_inline)) {
+        const int beam = cit.u.bg * kBeams + 16 * mt + m;
+        const double sb = (double)(beam < nbeam ? scale[beam] : 0.0f);
+        sb2 = sb * sb;
+        int sre = 0, sim = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int beam = cit.u.bg * kBeams + 16 * mt + 4 * q + v;
-            const double sb = (double)(beam < nbeam ? scale[beam] : 0.0f);
-            sb2[v] = sb * sb;
-        }
+        for (int ks = 0; ks < kPKS; ++ks)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sre = __builtin_amdgcn_sdot4(wre[ks][k], 0x01010101, sre, false);
+                sim = __builtin_amdgcn_sdot4(wim[ks][k], 0x01010101, sim, false);
+            }
+        // the four K groups of the beam are the lanes m, m+16, m+32, m+48
+        sre += swz_xor<16>(sre);
+        sim += swz_xor<16>(sim);
+        sre += xor32(sre, lane);
+        sim += xor32(sim, lane);
+        c8re = 8 * sre;
+        c8im = 8 * sim;
     };
 
     v4i fa[kPKS], fb[kPKS];
 #pragma unroll
     for (int ks = 0; ks < kPKS; ++ks) fa[ks] = fb[ks] = v4i{0, 0, 0, 0};
     load_weights();
-    item_scales();
+    item_consts();
     read_frags(lds, fa);
 
-    constexpr int L = LOGNAVG < 4 ? LOGNAVG : 4;
     constexpr int kTilesPerWin = LOGNAVG > 4 ? 1 << (LOGNAVG - 4) : 1;
     const int nwin = ntime >> LOGNAVG;
-    int64_t part[4] = {0, 0, 0, 0};
+    double part = 0.0;
     PItem cnext = cit;  // the consumer's next item
     pitem_next(cnext, grid, total, ntb, nbg, nchan);
     int ck = 0;         // consumer's stage within cit
@@ -481,56 +540,82 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
         const bool last = ck + 1 == kPStages;
         const bool more = !last || cnext.valid;
         if (more) {
-            // Stage i+1 has landed.  Younger than it: two stages of DMA, and
-            // the next item's weights while they were fetched behind it.
-            if (cnext.valid && ck > kPWStage && ck <= kPWStage + 3) wait_vm<3 * kPDma>();
-            else wait_vm<2 * kPDma>();
+            // Stage i+1 has landed.  Younger than it: kPSlots - 2 stages of
+            // DMA, and the next item's weights while they were fetched behind
+            // it (issued at stage kPWStage behind stage kPWStage + kPSlots).
+            if (cnext.valid && ck > kPWStage && ck < kPWStage + kPSlots)
+                wait_vm<(kPSlots - 2) * kPDma + kPWDma>();
+            else
+                wait_vm<(kPSlots - 2) * kPDma>();
             wait_lds();  // every read of stage i has returned: its slot is refilled now
             block_barrier();
-            produce(lds_base + (i & (kPSlots - 1)) * kPStage);
+            produce(lds_base + (i % kPSlots) * kPStage);
             if (ck == kPWStage && cnext.valid) pweights_dma(w, ninput, nbeam, cnext.u, lds_w, wave, lane);
-            read_frags(lds + ((i + 1) & (kPSlots - 1)) * kPStage, nxt);
+            read_frags(lds + ((i + 1) % kPSlots) * kPStage, nxt);
         }
         __builtin_amdgcn_sched_barrier(0);
-        v4i rr = v4i{0, 0, 0, 0}, ii = rr, ima = rr, imb = rr;
+        // D[sample][beam] = X W^T over the stage's 16 samples: P1 = R Wre,
+        // P2 = X' Wre, Q1 = R Wim, Q2 = X' Wim (R = 16 re, X' = 16 re + im + 8)
+        v4i p1 = v4i{0, 0, 0, 0}, p2 = p1, q1 = p1, q2 = p1;
 #pragma unroll
         for (int ks = 0; ks < kPKS; ++ks) {
             if (ks < nks) {
-                v4i xr, xi;
-                split_ci4(cur[ks], xr, xi);
-                rr = __builtin_amdgcn_mfma_i32_16x16x64_i8(wre[ks], xr, rr, 0, 0, 0);
-                ii = __builtin_amdgcn_mfma_i32_16x16x64_i8(wim[ks], xi, ii, 0, 0, 0);
-                ima = __builtin_amdgcn_mfma_i32_16x16x64_i8(wre[ks], xi, ima, 0, 0, 0);
-                imb = __builtin_amdgcn_mfma_i32_16x16x64_i8(wim[ks], xr, imb, 0, 0, 0);
+                v4i r, xo;
+                split_ci4_offset(cur[ks], r, xo);
+                p1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(r, wre[ks], p1, 0, 0, 0);
+                q2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(xo, wim[ks], q2, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(xo, wre[ks], p2, 0, 0, 0);
+                q1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(r, wim[ks], q1, 0, 0, 0);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        // the next item's weights (in LDS since its stage kPWStage + 4)
+        // the next item's weights (in LDS since its stage kPWStage + kPSlots)
         if (last && more) load_weights();
-        // detect and integrate: lane holds sample T0 + 256 qw + 16 ck + m of
-        // beams bg*32 + 16 mt + 4q + v
-        const int64_t t = (int64_t)cit.u.tb * kPItemT + 256 * qw + 16 * ck + m;
-        const int64_t uwin = t >> LOGNAVG;
-        const bool flush = (ck % kTilesPerWin) == kTilesPerWin - 1;
+        // Detect and integrate.  Lane: beam bg*32 + 16 mt + m, samples
+        // T0 + 256 qw + 16 ck + 4q + v (v = 0..3), so windows of up to 4
+        // samples are lane-local, 8 and 16 add the lanes 16 and 32 away, 32
+        // and 64 add consecutive stages.
+        const int64_t t0 = (int64_t)cit.u.tb * kPItemT + 256 * qw + 16 * ck + 4 * q;
+        const int beam = cit.u.bg * kBeams + 16 * mt + m;
+        const bool bok = beam < nbeam;
+        // |y|^2 in binary64: with at most 512 inputs |Re y|, |Im y| < 2^20, so
+        // every sample's power is an integer below 2^41 and a window's sum
+        // (up to 64 samples) one below 2^47, exact in binary64 whatever the
+        // order of the additions.
+        double e[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int yr = (rr[v] - ii[v]) >> 4;
-            const int yi = (ima[v] + imb[v]) >> 4;
-            int64_t p = (int64_t)yr * yr + (int64_t)yi * yi;
-            p = group_sum64<L>(p);
-            part[v] += p;
-            if (flush) {
-                const int beam = cit.u.bg * kBeams + 16 * mt + 4 * q + v;
-                if ((m & ((1 << L) - 1)) == 0 && uwin < nwin && beam < nbeam)
-                    out[((int64_t)beam * nchan + cit.u.f) * nwin + uwin] = (float)(sb2[v] * (double)part[v]);
-                part[v] = 0;
+            const int yr = (p1[v] >> 4) - q2[v] + q1[v] + c8im;
+            const int yi = (q1[v] >> 4) + p2[v] - p1[v] - c8re;
+            const double dr = (double)yr, di = (double)yi;
+            e[v] = __builtin_fma(dr, dr, di * di);
+        }
+        float *ob = out + ((int64_t)beam * nchan + cit.u.f) * nwin;
+        if constexpr (LOGNAVG == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (bok && t0 + v < nwin) ob[t0 + v] = (float)(sb2 * e[v]);
+        } else if constexpr (LOGNAVG == 1) {
+            const int64_t u0 = t0 >> 1;
+            if (bok && u0 < nwin) ob[u0] = (float)(sb2 * (e[0] + e[1]));
+            if (bok && u0 + 1 < nwin) ob[u0 + 1] = (float)(sb2 * (e[2] + e[3]));
+        } else {
+            double sum = (e[0] + e[1]) + (e[2] + e[3]);
+            if constexpr (LOGNAVG >= 3) sum += swz_xor_f64<16>(sum);
+            if constexpr (LOGNAVG >= 4) sum += xor32_f64(sum, lane);
+            part += sum;
+            constexpr int kLeadMask = LOGNAVG >= 4 ? 3 : LOGNAVG == 3 ? 1 : 0;
+            if ((ck % kTilesPerWin) == kTilesPerWin - 1) {
+                const int64_t u = t0 >> LOGNAVG;
+                if ((q & kLeadMask) == 0 && bok && u < nwin) ob[u] = (float)(sb2 * part);
+                part = 0.0;
             }
         }
         if (last) {
             cit = cnext;
             pitem_next(cnext, grid, total, ntb, nbg, nchan);
             ck = 0;
-            if (more) item_scales();
+            if (more) item_consts();
         } else {
             ++ck;
         }
