@@ -130,8 +130,9 @@ def time_launches(fn, reps, warm=2):
 def measured_peaks():
     """Sustainable rates of this device from the library's peak probes: dense
     MFMA (int8 and binary16, back-to-back MFMAs on 8 independent accumulators
-    per wave, no memory traffic) and HBM reads (a 2 GiB buffer streamed once
-    with 16-byte loads).  Best of 5 event-timed launches each."""
+    per wave, no memory traffic), LDS reads per CU (transposing 8-byte reads
+    and plain 16-byte reads) and HBM reads (a 2 GiB buffer streamed once with
+    16-byte loads).  Best of 5 event-timed launches each."""
     import torch
     import paper_1708_00720_amd as bfx
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
@@ -141,6 +142,16 @@ def measured_peaks():
         iters, nb = 2000, 4 * ncu
         _, _, best = time_launches(lambda: bfx.bfx_probe_mfma(kind, iters, nb, sink), 5)
         out[name] = round(bfx.bfx_probe_mfma_ops(kind, iters, nb) / (best * 1e-3) / 1e12, 1)
+    # LDS read bandwidth per CU (bytes per ns; bytes per clock at the 2.4 GHz
+    # peak clock): transposing 8-byte reads, as the X-engines' fragment
+    # reads, and plain 16-byte reads
+    for name, kind in (("lds_tr16", bfx.BFX_PROBE_LDS_TR16), ("lds_tr8", bfx.BFX_PROBE_LDS_TR8),
+                       ("lds_b128", bfx.BFX_PROBE_LDS_B128)):
+        iters, nb = 20000, ncu
+        _, _, best = time_launches(lambda: bfx.bfx_probe_lds(kind, iters, nb, sink), 5)
+        per_cu_ns = bfx.bfx_probe_lds_bytes(kind, iters, nb) / ncu / (best * 1e6)
+        out[f"{name}_bytes_per_ns_per_cu"] = round(per_cu_ns, 1)
+        out[f"{name}_bytes_per_clk_per_cu_at_2p4GHz"] = round(per_cu_ns / 2.4, 1)
     buf = torch.ones(1 << 29, dtype=torch.int32, device="cuda")  # 2 GiB
     nbytes = buf.numel() * 4
     _, _, best = time_launches(lambda: bfx.bfx_probe_read(buf, nbytes, 32 * ncu, sink), 5)

@@ -34,6 +34,20 @@ int64_t bfx_probe_mfma_ops(int32_t kind, int32_t iters, int32_t nblocks);
 bfx_status bfx_probe_read(const void *d_buf, int64_t nbytes, int32_t nblocks, int32_t *d_sink,
                           bfx_stream stream);
 
+#define BFX_PROBE_LDS_TR16 2 /* ds_read_b64_tr_b16 (transposing, 8 bytes per lane)  */
+#define BFX_PROBE_LDS_TR8 3  /* ds_read_b64_tr_b8                                   */
+#define BFX_PROBE_LDS_B128 4 /* ds_read_b128 (16 bytes per lane, no transpose)      */
+
+/* Enqueue the LDS read probe: nblocks workgroups of 8 waves, each wave issuing
+ * 12 x iters LDS reads of `kind` inside a 16 KiB LDS buffer (the X-engines'
+ * conflict-free transposing pattern for the tr kinds, consecutive 16-byte
+ * chunks for b128) and folding the results into d_sink (device
+ * int32[nblocks], written only in a case the data never produces).
+ * bfx_probe_lds_bytes gives the bytes it reads.  BFX_EINVAL for a bad kind,
+ * iters <= 0, nblocks outside [1, 2^20] or a NULL d_sink.                    */
+bfx_status bfx_probe_lds(int32_t kind, int32_t iters, int32_t nblocks, int32_t *d_sink, bfx_stream stream);
+int64_t bfx_probe_lds_bytes(int32_t kind, int32_t iters, int32_t nblocks);
+
 #ifdef __cplusplus
 }
 #endif

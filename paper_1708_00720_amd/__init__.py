@@ -72,6 +72,8 @@ _SIGS = {
     "bfx_probe_mfma": (_st, [_i32, _i32, _i32, _vp, _vp]),
     "bfx_probe_mfma_ops": (_i64, [_i32, _i32, _i32]),
     "bfx_probe_read": (_st, [_vp, _i64, _i32, _vp, _vp]),
+    "bfx_probe_lds": (_st, [_i32, _i32, _i32, _vp, _vp]),
+    "bfx_probe_lds_bytes": (_i64, [_i32, _i32, _i32]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -285,6 +287,17 @@ def bfx_probe_mfma_ops(kind: int, iters: int, nblocks: int) -> int:
 
 def bfx_probe_read(d_buf, nbytes: int, nblocks: int, d_sink, stream=None):
     _check(_lib.bfx_probe_read(_addr(d_buf), nbytes, nblocks, _addr(d_sink), _stream(stream)))
+
+
+BFX_PROBE_LDS_TR16, BFX_PROBE_LDS_TR8, BFX_PROBE_LDS_B128 = 2, 3, 4
+
+
+def bfx_probe_lds(kind: int, iters: int, nblocks: int, d_sink, stream=None):
+    _check(_lib.bfx_probe_lds(kind, iters, nblocks, _addr(d_sink), _stream(stream)))
+
+
+def bfx_probe_lds_bytes(kind: int, iters: int, nblocks: int) -> int:
+    return int(_lib.bfx_probe_lds_bytes(kind, iters, nblocks))
 
 
 # ------------------------------------------------------------------ conveniences

@@ -184,3 +184,22 @@ def test_tengine_argument_errors(kw, code):
         bfx.bfx_tengine(FAKE, args["nchan"], args["ninput"], args["nspec"], args["chan0"], args["nfft"],
                         args["mix_num"], args["mix_den"], args["scale"], FAKE, out=args["out"], stream=0)
     assert ei.value.status == code
+
+
+def test_probe_argument_errors_and_counts():
+    """The peak probes validate on the host and count their work exactly."""
+    for call in (lambda: bfx.bfx_probe_mfma(7, 10, 4, FAKE, stream=0),
+                 lambda: bfx.bfx_probe_mfma(bfx.BFX_PROBE_MFMA_I8, 0, 4, FAKE, stream=0),
+                 lambda: bfx.bfx_probe_lds(bfx.BFX_PROBE_MFMA_F16, 10, 4, FAKE, stream=0),
+                 lambda: bfx.bfx_probe_lds(bfx.BFX_PROBE_LDS_TR16, 10, 0, FAKE, stream=0),
+                 lambda: bfx.bfx_probe_lds(bfx.BFX_PROBE_LDS_B128, 10, 4, 0, stream=0),
+                 lambda: bfx.bfx_probe_read(FAKE + 8, 1024, 4, FAKE, stream=0)):
+        with pytest.raises(bfx.BfxError) as ei:
+            call()
+        assert ei.value.status == bfx.BFX_EINVAL
+    # 8 waves x 64 lanes x 12 reads per iteration
+    assert bfx.bfx_probe_lds_bytes(bfx.BFX_PROBE_LDS_TR16, 3, 5) == 8 * 512 * 12 * 3 * 5
+    assert bfx.bfx_probe_lds_bytes(bfx.BFX_PROBE_LDS_B128, 3, 5) == 16 * 512 * 12 * 3 * 5
+    assert bfx.bfx_probe_lds_bytes(9, 3, 5) == -1
+    # 8 waves x 8 MFMAs per iteration, 2 x 32 x 32 x K ops each
+    assert bfx.bfx_probe_mfma_ops(bfx.BFX_PROBE_MFMA_I8, 3, 5) == 2 * 32 * 32 * 32 * 64 * 3 * 5
