@@ -67,7 +67,7 @@ constexpr int kLdsBytes = kABytes + kBBytes + kTw2Bytes;  // two workgroups per 
 // Buffer A (pass 1 -> 2) uses the additive pad_a (fft16.h).
 // Buffer B (pass 2 -> 3): butterflies above 128 of each 256 block in reversed
 // order (piB), then x ^ (((x >> 8) & 15) << 4): conflict-free for the pass-2
-// writes and for both half-waves' pass-3 reads.
+// writes (16-lane groups) and for both half-waves' pass-3 reads.
 __device__ __forceinline__ int swz_b(int x) {
     const int b = x & 255;
     const int y = (x & ~255) | (b <= 128 ? b : 384 - b);

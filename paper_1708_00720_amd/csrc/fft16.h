@@ -13,6 +13,10 @@ namespace {
 // exchange differ by constants and fold into the instructions' offsets.
 //   pad_a: pass-1 writes 16 j + r and the reads j + 256 r that follow;
 //   pad_b: writes (j / 16) 256 + j % 16 + 16 r and the reads j + 256 r.
+// The LDS serves 8-byte writes 16 lanes at a time over 32 banks; there the
+// pad_a writes put two lanes on each bank pair (a two-way conflict on the
+// pass-1 writes only).  The XOR swizzle x ^ ((x >> 4) & 15) avoids it at two
+// vector operations per write; both kernels time the same either way.
 constexpr int kPadAElems = 4096 + 4096 / 32;
 constexpr int kPadBElems = 4096 + 3 * (4096 / 64) + 2 * (4096 / 128);
 __device__ __forceinline__ int pad_a(int x) { return x + (x >> 5); }
