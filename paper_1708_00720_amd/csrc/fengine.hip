@@ -208,16 +208,17 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
                 if (self128) w = v[15 - c];
                 if (self0) w = v[(16 - c) & 15];
                 // X_a = (z + conj w)/2, X_b = (z - conj w)/(2i) = -i (z - conj w)/2
-                const float2 xa{0.5f * (z.x + w.x), 0.5f * (z.y - w.y)};
-                const float2 xb{0.5f * (z.y + w.y), -0.5f * (z.x - w.x)};
                 if (CI8) {
-                    const float sc = scale[k];
-                    const uint32_t word = (uint32_t)(uint8_t)requant(xa.x, sc) |
-                                          ((uint32_t)(uint8_t)requant(xa.y, sc) << 8) |
-                                          ((uint32_t)(uint8_t)requant(xb.x, sc) << 16) |
-                                          ((uint32_t)(uint8_t)requant(xb.y, sc) << 24);
+                    // the halving rides on the scale: fl(s fl(x / 2)) = fl((s / 2) x)
+                    const float hs = 0.5f * scale[k];
+                    const uint32_t word = (uint32_t)(uint8_t)requant(z.x + w.x, hs) |
+                                          ((uint32_t)(uint8_t)requant(z.y - w.y, hs) << 8) |
+                                          ((uint32_t)(uint8_t)requant(z.y + w.y, hs) << 16) |
+                                          ((uint32_t)(uint8_t)requant(w.x - z.x, hs) << 24);
                     q[c] = uint4{q[c].y, q[c].z, q[c].w, word};
                 } else {
+                    const float2 xa{0.5f * (z.x + w.x), 0.5f * (z.y - w.y)};
+                    const float2 xb{0.5f * (z.y + w.y), -0.5f * (z.x - w.x)};
                     float4 *o = (float4 *)((float *)out +
                                            (((int64_t)s * kChan + k) * ninput + i0 + 2 * p) * 2);
                     *o = float4{xa.x, xa.y, xb.x, xb.y};

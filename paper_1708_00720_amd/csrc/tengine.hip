@@ -85,8 +85,9 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
             tw3[r] = g_tw[(r * m3) & (kN - 1)];
         }
     }
-    // output n = j + 256 r has the shift sign (-1)^j
-    const float sgn = (j & 1) ? -inv_n : inv_n;
+    // output n = j + 256 r has the shift sign (-1)^j; the sign, 1/nfft and the
+    // scale ride on the lane's mixer phasor
+    const float sgn_scale = ((j & 1) ? -inv_n : inv_n) * scale;
 
     for (int B = blockIdx.x; B < total_flat; B += gridDim.x) {
         int s, g;
@@ -98,12 +99,15 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) xs[r] = *(const uint4 *)(src + (int64_t)(256 * r) * ninput * 2);
         }
-        // mixer phasor of this lane's output t = s N + j (exact phase index)
+        // mixer phasor of this lane's output t = s N + j (exact phase index),
+        // times the shift sign, 1/nfft and the scale
         float2 ph0;
         {
             const uint64_t t0 = (uint64_t)s * kN + j;
             const uint32_t m = (uint32_t)(((uint64_t)mix_n * (t0 % mix_d)) % mix_d);
             sincospif(2.0f * ((float)m * inv_d), &ph0.y, &ph0.x);
+            ph0.x *= sgn_scale;
+            ph0.y *= sgn_scale;
         }
         // codes of the 8 inputs at each of the lane's 16 outputs
         uint32_t code[16][CI4 ? 2 : 4];
@@ -139,12 +143,16 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
                 v[r] = r == 0 ? x : cmul(x, tw3[r]);
             }
             dft16(v);
-            // v[r] = FFT(conj X)[n], n = j + 256 r:  z = conj(v) (-1)^n / N
+            // v[r] = FFT(conj X)[n], n = j + 256 r:  z = conj(v) (-1)^n / N, and
+            // scale z e^{i phase} = conj(v) w with w = E_r ph0 (sign, 1/N, scale in
+            // ph0).  w is formed anew for each input: hoisted out of the input
+            // loop, its 16 values would take 32 more registers than there are.
+            asm volatile("" : "+v"(ph0.x), "+v"(ph0.y));
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float2 z{sgn * v[r].x, -sgn * v[r].y};
-                const float2 zm = cmul(cmul(z, E.e[r]), ph0);
-                const int qr = quant(scale * zm.x, lim), qi = quant(scale * zm.y, lim);
+                const float2 w = cmul(E.e[r], ph0);
+                const float2 zm{v[r].x * w.x + v[r].y * w.y, v[r].x * w.y - v[r].y * w.x};
+                const int qr = quant(zm.x, lim), qi = quant(zm.y, lim);
                 if (CI4) {
                     const uint32_t b = (((uint32_t)qr & 15u) << 4) | ((uint32_t)qi & 15u);
                     const int w = ii >> 2, sh = 8 * (ii & 3);
