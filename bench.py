@@ -402,6 +402,49 @@ def row_batched(reps):
     return r
 
 
+def row_share_g8(reps):
+    """One GPU's share of the headline gulp when a node of 8 GPUs shards it
+    by channel: 704 inputs x 24 channels x 1000 samples, ci4 (the corner
+    turn that would deliver it is not run)."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    import synth
+    F = N_CHAN // 8
+    raw = synth.voltages(2, N_TIME, F, N_INPUT, "ci4", 2.5, 7, gulp=0)
+    x = torch.from_numpy(raw.reshape(-1)).cuda()
+    plan = bfx.bfx_xengine_create(N_INPUT, F, "ci4")
+    tune_us = bfx.bfx_xengine_autotune(plan, N_TIME)
+    acc = bfx.visibilities_buffer(plan)
+    avg, med, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(plan, x, N_TIME, acc, overwrite=True), reps)
+    cmac = F * N_TIME * N_INPUT * (N_INPUT + 1) // 2
+    nbytes = N_TIME * F * N_INPUT + F * N_INPUT * (N_INPUT + 1) // 2 * 8
+    variant = bfx.bfx_xengine_variant(plan)
+    plan.close()
+    # The same share for 4 consecutive gulps in one batched launch (4
+    # subarrays of 704 x 24): 4x the work items, so the grid's last round of
+    # items is no longer mostly empty.
+    bplan = bfx.bfx_xengine_create_batched([N_INPUT] * 4, [F] * 4, "ci4")
+    btune = bfx.bfx_xengine_autotune(bplan, N_TIME)
+    arena = torch.empty(bfx.bfx_xengine_in_bytes(bplan, N_TIME), dtype=torch.uint8, device="cuda")
+    for k in range(4):
+        io, _ = bfx.bfx_xengine_sub_offsets(bplan, k, N_TIME)
+        arena[io:io + x.numel()].copy_(x)
+    bacc = bfx.visibilities_buffer(bplan)
+    bavg, _, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(bplan, arena, N_TIME, bacc, overwrite=True),
+                               reps)
+    bplan.close()
+    r = _row("xengine_int_kernel<ci4>", f"704 inputs x {F} channels x 1000 samples ci4 (one GPU's share "
+             "of the headline gulp at 8 GPUs)", avg, med, 8 * cmac, "ops", PEAK_INT8_TOPS, "TOP/s", "mfma",
+             nbytes, {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
+                      "kernel_variant": variant,
+                      "autotune_us": [round(t, 1) for t in tune_us],
+                      "batched_4_gulps": {"avg_launch_us": round(bavg * 1e3, 2),
+                                          "us_per_gulp": round(bavg * 1e3 / 4, 2),
+                                          "frac": round(8 * 4 * cmac / (bavg * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4),
+                                          "autotune_us": [round(t, 1) for t in btune]}})
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,7 +464,7 @@ def main():
     ap.add_argument("--graph-replays", type=int, default=60,
                     help="replays of the captured 4-gulp ring cycle (timed one by one)")
     ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "beamform_ci4", "tengine",
-                                           "batched"],
+                                           "batched", "share_g8"],
                     help="only time one row (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -456,7 +499,7 @@ def main():
     if args.only_row:
         fn = {"fengine": row_fengine, "xf16": lambda r: row_xengine_f16(r)[0],
               "beamform": row_beamform, "beamform_ci4": row_beamform_ci4, "tengine": row_tengine,
-              "batched": row_batched}[args.only_row]
+              "batched": row_batched, "share_g8": row_share_g8}[args.only_row]
         print(json.dumps(fn(args.row_reps)), flush=True)
         return
     if args.profile_launches:
@@ -602,6 +645,8 @@ def main():
         rows["beamform_ci4"] = row_beamform_ci4(args.row_reps)
         print("[bench] row: batched", file=sys.stderr, flush=True)
         rows["batched"] = row_batched(args.row_reps)
+        print("[bench] row: one GPU's share at 8 GPUs", file=sys.stderr, flush=True)
+        rows["share_g8"] = row_share_g8(args.row_reps)
         torch.cuda.empty_cache()
 
     cpu = None
