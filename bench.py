@@ -402,6 +402,33 @@ def row_batched(reps):
     return r
 
 
+def row_fx_xengine(reps):
+    """The X half of the F+X chain: the integer X-engine on the F-engine's ci8
+    output shape, 256 inputs x 2048 channels x 512 spectra (rounded Gaussian
+    sigma 8 codes stand in for the channelized data)."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    N, F, T = 256, 2048, 512
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.clamp(torch.round(8.0 * torch.randn(T * F * N * 2, device="cuda", generator=g)),
+                    -127, 127).to(torch.int8)
+    plan = bfx.bfx_xengine_create(N, F, "ci8")
+    tune_us = bfx.bfx_xengine_autotune(plan, T)
+    acc = bfx.visibilities_buffer(plan)
+    avg, med, _ = time_launches(lambda: bfx.bfx_xengine_accumulate(plan, x, T, acc, overwrite=True), reps)
+    cmac = F * T * N * (N + 1) // 2
+    nbytes = T * F * N * 2 + F * N * (N + 1) // 2 * 8
+    r = _row("xengine_int_kernel<ci8>", "256 inputs x 2048 channels x 512 spectra ci8 (the X half of F+X)",
+             avg, med, nbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", nbytes,
+             {"tcmac_per_s": round(cmac / (avg * 1e-3) / 1e12, 2),
+              "int8_mfma_frac": round(8 * cmac / (avg * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4),
+              "kernel_variant": bfx.bfx_xengine_variant(plan),
+              "autotune_us": [round(t, 1) for t in tune_us]})
+    plan.close()
+    del x, acc
+    return r
+
+
 def row_share_g8(reps):
     """One GPU's share of the headline gulp when a node of 8 GPUs shards it
     by channel: 704 inputs x 24 channels x 1000 samples, ci4 (the corner
@@ -464,7 +491,7 @@ def main():
     ap.add_argument("--graph-replays", type=int, default=60,
                     help="replays of the captured 4-gulp ring cycle (timed one by one)")
     ap.add_argument("--only-row", choices=["fengine", "xf16", "beamform", "beamform_ci4", "tengine",
-                                           "batched", "share_g8"],
+                                           "batched", "share_g8", "fx_xengine"],
                     help="only time one row (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -499,7 +526,7 @@ def main():
     if args.only_row:
         fn = {"fengine": row_fengine, "xf16": lambda r: row_xengine_f16(r)[0],
               "beamform": row_beamform, "beamform_ci4": row_beamform_ci4, "tengine": row_tengine,
-              "batched": row_batched, "share_g8": row_share_g8}[args.only_row]
+              "batched": row_batched, "share_g8": row_share_g8, "fx_xengine": row_fx_xengine}[args.only_row]
         print(json.dumps(fn(args.row_reps)), flush=True)
         return
     if args.profile_launches:
@@ -645,6 +672,8 @@ def main():
         rows["beamform_ci4"] = row_beamform_ci4(args.row_reps)
         print("[bench] row: batched", file=sys.stderr, flush=True)
         rows["batched"] = row_batched(args.row_reps)
+        print("[bench] row: X half of F+X", file=sys.stderr, flush=True)
+        rows["fx_xengine"] = row_fx_xengine(args.row_reps)
         print("[bench] row: one GPU's share at 8 GPUs", file=sys.stderr, flush=True)
         rows["share_g8"] = row_share_g8(args.row_reps)
         torch.cuda.empty_cache()
