@@ -99,3 +99,30 @@ def test_workload_sampled():
     inputs = [0, 1, 7, 8, 100, 128, 200, 255, 31, 32, 63, 64, 65, 129, 190, 254]
     total, nflag, ndiff = _check(x, gre, gim, chan0, mix_num, mix_den, scale, "ci4", (0, 3, 126), inputs)
     print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one")
+
+
+@pytest.mark.parametrize("out", ["ci8", "ci4"])
+def test_fewest_inputs_odd_frames_no_mixer(out):
+    """One group of 8 inputs (the smallest), 9 frames (the last frame group
+    of the grid is partly empty), no mixer (mix_num 0): every frame's codes
+    against the oracle."""
+    nspec, nchan, ninput, chan0 = 9, NFFT, 8, 0
+    banner(f"tengine {out} 8 inputs, 9 frames, no mixer")
+    x = synth.voltages(13, nspec, nchan, ninput, "ci8", 8.0, 127)
+    scale = 16.0 if out == "ci8" else 4.0
+    gre, gim = _run(x, nchan, ninput, nspec, chan0, 0, 1, scale, out)
+    total, nflag, ndiff = _check(x, gre, gim, chan0, 0, 1, scale, out, tuple(range(nspec)), list(range(ninput)))
+    print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one")
+
+
+def test_largest_mixer_denominator():
+    """mix_den = 2^31 - 1 (the largest accepted; prime, so the phase index
+    never repeats within the run) with mix_num = 7: frame 0 against the
+    oracle, whose exact integer phase index the kernel must reproduce."""
+    nspec, nchan, ninput, chan0 = 2, NFFT, 16, 0
+    mix_num, mix_den, scale = 7, 2 ** 31 - 1, 16.0
+    banner("tengine ci8 mix_den 2^31-1")
+    x = synth.voltages(14, nspec, nchan, ninput, "ci8", 8.0, 127)
+    gre, gim = _run(x, nchan, ninput, nspec, chan0, mix_num, mix_den, scale, "ci8")
+    total, nflag, ndiff = _check(x, gre, gim, chan0, mix_num, mix_den, scale, "ci8", (0,), list(range(ninput)))
+    print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one")
