@@ -275,8 +275,18 @@ def row_xengine_f16(reps, x=None):
     run64 = torch.zeros(acc.numel(), dtype=torch.float64, device="cuda")
     davg, dmed, _ = time_launches(lambda: bfx.bfx_xengine_dump(plan, acc, None, run64), max(3, reps // 2))
     dbytes = acc.numel() * 4 + run64.numel() * 16
+    # the same gulp folded straight into the running sum (fused epilogue):
+    # no binary32 buffer written and read back
+    favg, fmed, _ = time_launches(lambda: bfx.bfx_xengine_accumulate_run64(plan, x, T, run64), max(3, reps // 2))
+    fbytes = T * F * N * 4 + run64.numel() * 16
     d = _row("dump_kernel<float> (FP64 running sum)", "2048 x 131328 cf32 visibilities",
-             davg, dmed, dbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", dbytes)
+             davg, dmed, dbytes, "bytes", PEAK_HBM_GBPS, "GB/s", "hbm", dbytes,
+             {"fused_accumulate_run64": {
+                 "avg_launch_us": round(favg * 1e3, 2),
+                 "separate_accumulate_plus_dump_us": round((avg + davg) * 1e3, 2),
+                 "algorithmic_hbm_bytes_per_launch": fbytes,
+                 "hbm_GBps_algorithmic": round(fbytes / (favg * 1e-3) / 1e9, 1),
+                 "fp16_mfma_frac": round(8 * cmac / (favg * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, 4)}})
     plan.close()
     del acc, run64
     return r, d, x
@@ -524,7 +534,7 @@ def main():
         print(json.dumps(measured_peaks()), flush=True)
         return
     if args.only_row:
-        fn = {"fengine": row_fengine, "xf16": lambda r: row_xengine_f16(r)[0],
+        fn = {"fengine": row_fengine, "xf16": lambda r: dict(zip(("xengine_f16", "dump_run64"), row_xengine_f16(r)[:2])),
               "beamform": row_beamform, "beamform_ci4": row_beamform_ci4, "tengine": row_tengine,
               "batched": row_batched, "share_g8": row_share_g8, "fx_xengine": row_fx_xengine}[args.only_row]
         print(json.dumps(fn(args.row_reps)), flush=True)

@@ -235,6 +235,25 @@ bfx_status bfx_xengine_accumulate_batched_noalloc(int32_t nsub, const int32_t *n
 bfx_status bfx_xengine_dump(bfx_xengine *plan, const void *d_acc, void *d_out, double *d_run64,
                             bfx_stream stream);
 
+/* Correlate one binary16 gulp and fold it straight into a binary64 running
+ * sum (the X-engine's cross-multiply, Sec. 2.2 and 7, with the dump of the
+ * Sec. 4.1 accumulate block fused into its store):
+ *   d_run64[k] += (double)V_k,
+ * V the binary32 visibilities that bfx_xengine_accumulate with
+ * BFX_ACC_OVERWRITE would write -- so the result has the same bits as that
+ * call followed by bfx_xengine_dump(plan, d_acc, NULL, d_run64) -- without
+ * writing and reading back the binary32 buffer.
+ *   plan     a single-array BFX_CF16 plan (BFX_ENOTSUP otherwise);
+ *   d_in     device cf16 gulp [ntime][nchan][ninput], 16-byte aligned;
+ *   ntime    1 .. 65535 samples (one launch; BFX_ERANGE beyond: longer
+ *            integrations accumulate into a binary32 buffer and dump it);
+ *   d_run64  device binary64 [nchan][p][2] running sum (2 x out_bytes),
+ *            16-byte aligned, read and written.
+ * Does not change the plan's accumulation count.  Argument errors are
+ * returned before anything is enqueued.                                     */
+bfx_status bfx_xengine_accumulate_run64(bfx_xengine *plan, const void *d_in, int64_t ntime, double *d_run64,
+                                        bfx_stream stream);
+
 /* ------------------------------------------------------------------------ */
 /* F-engine (Sec. 2.2 FFT and quantize modules; Sec. 6: 204.8 MS/s real
  * samples become 4096 channels, i.e. a real transform of 2N points keeps the

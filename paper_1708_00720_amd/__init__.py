@@ -63,6 +63,7 @@ _SIGS = {
     "bfx_tune_cache_lookup": (_i32, [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p]),
     "bfx_xengine_accumulate": (_st, [_vp, _vp, _i64, _vp, _u32, _vp]),
     "bfx_xengine_dump": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "bfx_xengine_accumulate_run64": (_st, [_vp, _vp, _i64, _vp, _vp]),
     "bfx_fengine": (_st, [_vp, _i32, _i32, _i64, _vp, _vp, ctypes.c_int, _vp]),
     "bfx_beamform_detect": (_st, [_vp, _vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp]),
     "bfx_xengine_accumulate_batched_noalloc": (_st, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -240,6 +241,10 @@ def bfx_xengine_accumulate(plan: Plan, d_in, ntime: int, d_acc, overwrite: bool 
 def bfx_xengine_dump(plan: Plan, d_acc, d_out=None, d_run64=None, stream=None):
     _check(_lib.bfx_xengine_dump(plan.handle, _addr(d_acc), _addr(d_out), _addr(d_run64),
                                  _stream(stream)))
+
+
+def bfx_xengine_accumulate_run64(plan: Plan, d_in, ntime: int, d_run64, stream=None):
+    _check(_lib.bfx_xengine_accumulate_run64(plan.handle, _addr(d_in), ntime, _addr(d_run64), _stream(stream)))
 
 
 def bfx_fengine(d_in, ninput: int, nfft: int, nspec: int, d_scale, d_out, out="ci8", stream=None):

@@ -34,8 +34,6 @@ bfx_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Defined with the kernels.
-hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
-                              float *out, bool overwrite, int variant, hipStream_t s);
 hipError_t launch_dump(bool is_int, const void *acc, void *out, double *run64, int64_t n,
                        hipStream_t s);
 hipError_t launch_fengine(const int8_t *in, int32_t ninput, int32_t nfft, int64_t nspec,
@@ -587,8 +585,8 @@ bfx_status bfx_xengine_accumulate(bfx_xengine *plan, const void *d_in, int64_t n
         for (int64_t t0 = 0; t0 < ntime && e == hipSuccess; t0 += kLaunchMaxTime) {
             const int64_t nt = ntime - t0 < kLaunchMaxTime ? ntime - t0 : kLaunchMaxTime;
             const uint8_t *src = (const uint8_t *)d_in + t0 * sb.nchan * sb.ninput * 4;
-            e = launch_xengine_f16(src, nt, sb.nchan, sb.ninput, (float *)d_acc,
-                                   overwrite && t0 == 0, plan->variant, s);
+            e = launch_xengine_f16(src, nt, sb.nchan, sb.ninput, d_acc,
+                                   overwrite && t0 == 0 ? F16Out::kStore : F16Out::kAdd, plan->variant, s);
         }
     } else {
         const bool ci4 = plan->in == BFX_CI4;
@@ -636,6 +634,27 @@ bfx_status bfx_xengine_dump(bfx_xengine *plan, const void *d_acc, void *d_out, d
         return fail(BFX_ENOTSUP, "running sums of batched arenas are not supported");
     hipError_t e = launch_dump(is_int, d_acc, copy ? d_out : nullptr, d_run64, n, s);
     if (e != hipSuccess) return hip_fail(e, "dump launch");
+    return BFX_OK;
+}
+
+bfx_status bfx_xengine_accumulate_run64(bfx_xengine *plan, const void *d_in, int64_t ntime, double *d_run64,
+                                        bfx_stream stream) {
+    g_detail[0] = 0;
+    if (!plan) return fail(BFX_EINVAL, "plan is NULL");
+    if (!d_in || !d_run64) return fail(BFX_EINVAL, "d_in / d_run64 is NULL");
+    if (!aligned16(d_in) || !aligned16(d_run64))
+        return fail(BFX_EINVAL, "d_in and d_run64 must be 16-byte aligned");
+    if (plan->in != BFX_CF16 || plan->batched)
+        return fail(BFX_ENOTSUP, "the fused running sum is built for single-array cf16 plans");
+    if (ntime <= 0) return fail(BFX_EINVAL, "ntime=%lld must be positive", (long long)ntime);
+    if (ntime > kLaunchMaxTime)
+        return fail(BFX_ERANGE, "ntime=%lld: the fused running sum takes at most %lld samples per call "
+                                "(one launch); accumulate longer integrations into a binary32 buffer "
+                                "and dump it", (long long)ntime, (long long)kLaunchMaxTime);
+    const Sub &sb = plan->subs[0];
+    hipError_t e = launch_xengine_f16(d_in, ntime, sb.nchan, sb.ninput, d_run64, F16Out::kAddRun64,
+                                      plan->variant, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "X-engine launch");
     return BFX_OK;
 }
 

@@ -65,6 +65,14 @@ int xengine_num_variants(bfx_dtype in, bool batched);
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan,
                               int32_t ninput, int32_t *out, bool overwrite, int variant, hipStream_t s);
 
+// Binary16 X-engine over one contiguous cf16 array (`nt` <= kLaunchMaxTime
+// rows from `in`).  Its output: add V to the binary32 buffer `out`, store it
+// there, or add (double)V to the binary64 running sum `out` (16-byte
+// elements, the same packed lower triangle).
+enum class F16Out { kAdd, kStore, kAddRun64 };
+hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput, void *out,
+                              F16Out mode, int variant, hipStream_t s);
+
 // Per-subarray record of a batched plan (device table, built at plan
 // creation).  Subarray k's gulp of ntime samples starts at byte
 // ntime * in_row_off of the input arena and is [ntime][nchan][ninput]

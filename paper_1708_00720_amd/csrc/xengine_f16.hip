@@ -75,6 +75,9 @@ __device__ __forceinline__ v8h read_frag16(const uint8_t *p) {
     return v8h{l[0], l[1], l[2], l[3], h[0], h[1], h[2], h[3]};
 }
 
+// Epilogue modes (the loop's `overwrite` argument).
+constexpr int kAddF32 = 0, kStoreF32 = 1, kAddF64 = 2;
+
 struct F16Consumer {
     static constexpr int kWaves = 8;
     static constexpr int kThreads = 64 * kWaves;
@@ -130,16 +133,19 @@ struct F16Consumer {
             float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
     }
 
+    // mode: kAddF32 adds V to the binary32 buffer, kStoreF32 stores it,
+    // kAddF64 adds (double)V to a binary64 running sum (16-byte elements).
     __device__ static __forceinline__ void epilogue(const WaveJob &j, const Item &it, const Acc &acc,
-                                                    int lane, int overwrite) {
+                                                    int lane, int mode) {
         const int ninput = it.ninput;
         uint8_t *obase = (uint8_t *)it.out + (int64_t)j.ochan * it.out_chan_bytes;
         const int g = lane >> 5;
         const int odd = lane & 1;
         const int il = j.rblk * kBlk + 2 * g + odd;                  // row of d = 0
         const int jl = j.cblk * kBlk + 32 * j.ch + ((lane & 31) >> 1);  // column of c = 0
-        const uint32_t base = (uint32_t)((il * (il + 1) / 2 + jl) * 8);
-        const uint32_t step = (uint32_t)(il * 8);
+        const uint32_t es = mode == kAddF64 ? 16 : 8;                 // bytes per complex element
+        const uint32_t base = (uint32_t)(il * (il + 1) / 2 + jl) * es;
+        const uint32_t step = (uint32_t)il * es;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
@@ -152,8 +158,8 @@ struct F16Consumer {
                 const int jj = jl + 16 * c;
                 auto dst = [&](int s) {
                     const int d = 16 * r + 4 * s;
-                    return (float2 *)(obase + base + (uint32_t)(16 * c * 8) + (uint32_t)d * step +
-                                      (uint32_t)(d * (d + 1) / 2 * 8));
+                    return obase + base + (uint32_t)(16 * c) * es + (uint32_t)d * step +
+                           (uint32_t)(d * (d + 1) / 2) * es;
                 };
                 auto ok = [&](int s) {
                     const int i = il + 16 * r + 4 * s;
@@ -177,13 +183,32 @@ struct F16Consumer {
                     const float ore = b2 + a3, oim = b3 - a2;
                     res[s] = float2{odd ? ore : ere, odd ? oim : eim};
                 }
-                if (!overwrite) {
+                if (mode == kAddF64) {
+                    // the binary32 result, converted exactly, into the running
+                    // sum: all old values first, then the sums, then the stores
+                    double2 old[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        old[s] = double2{0.0, 0.0};
+                        if (ok(s)) old[s] = *(const double2 *)dst(s);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        old[s] = double2{old[s].x + (double)res[s].x, old[s].y + (double)res[s].y};
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        if (ok(s)) *(double2 *)dst(s) = old[s];
+                    continue;
+                }
+                if (mode == kAddF32) {
                     // all old values first, then the sums, then the stores
                     float2 old[4];
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         old[s] = float2{0.0f, 0.0f};
-                        if (ok(s)) old[s] = *dst(s);
+                        if (ok(s)) old[s] = *(const float2 *)dst(s);
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -192,7 +217,7 @@ struct F16Consumer {
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    if (ok(s)) *dst(s) = res[s];
+                    if (ok(s)) *(float2 *)dst(s) = res[s];
             }
         }
     }
@@ -222,9 +247,10 @@ hipError_t set_attributes() {
 
 }  // namespace
 
-hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput,
-                              float *out, bool overwrite, int variant, hipStream_t s) {
+hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t ninput, void *out,
+                              F16Out mode, int variant, hipStream_t s) {
     if (variant < 0 || variant >= kF16Variants) return hipErrorInvalidValue;
+    const int m = mode == F16Out::kAdd ? kAddF32 : mode == F16Out::kStore ? kStoreF32 : kAddF64;
     int num_cus = 0;
     const hipError_t e = g_init.ensure(set_attributes, &num_cus);
     if (e != hipSuccess) return e;
@@ -233,7 +259,7 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     w.out = out;
     w.bps = 4;
     w.t_stride = (int64_t)nchan * ninput * 4;
-    w.out_chan_bytes = (int64_t)ninput * (ninput + 1) / 2 * 8;
+    w.out_chan_bytes = (int64_t)ninput * (ninput + 1) / 2 * (m == kAddF64 ? 16 : 8);
     w.nchan = nchan;
     w.ninput = ninput;
     w.nb = (ninput + kBlk - 1) / kBlk;
@@ -243,7 +269,7 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(num_cus, total_flat);
     hipLaunchKernelGGL(kF16[variant], dim3((unsigned)grid), dim3(F16Consumer::kThreads), kLdsBytes, s, w,
-                       (int)nt, (int)total_flat, (int)overwrite);
+                       (int)nt, (int)total_flat, m);
     return hipGetLastError();
 }
 

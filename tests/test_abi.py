@@ -203,3 +203,21 @@ def test_probe_argument_errors_and_counts():
     assert bfx.bfx_probe_lds_bytes(9, 3, 5) == -1
     # 8 waves x 8 MFMAs per iteration, 2 x 32 x 32 x K ops each
     assert bfx.bfx_probe_mfma_ops(bfx.BFX_PROBE_MFMA_I8, 3, 5) == 2 * 32 * 32 * 32 * 64 * 3 * 5
+
+
+def test_accumulate_run64_argument_errors():
+    """The fused binary64 running sum: cf16 single-array plans, 1..65535
+    samples, aligned non-NULL buffers; checked before any launch."""
+    p = bfx.bfx_xengine_create(64, 2, "cf16")
+    for args, code in (((FAKE, 0, FAKE), bfx.BFX_EINVAL), ((FAKE, 65536, FAKE), bfx.BFX_ERANGE),
+                       ((FAKE + 8, 16, FAKE), bfx.BFX_EINVAL), ((FAKE, 16, 0), bfx.BFX_EINVAL)):
+        with pytest.raises(bfx.BfxError) as ei:
+            bfx.bfx_xengine_accumulate_run64(p, *args, stream=0)
+        assert ei.value.status == code, args
+    p.close()
+    for dtype in ("ci8", "ci4"):
+        p = bfx.bfx_xengine_create(64, 2, dtype)
+        with pytest.raises(bfx.BfxError) as ei:
+            bfx.bfx_xengine_accumulate_run64(p, FAKE, 16, FAKE, stream=0)
+        assert ei.value.status == bfx.BFX_ENOTSUP
+        p.close()

@@ -206,3 +206,29 @@ def test_dump_full_size_running_sum():
     assert torch.equal(out, acc)
     assert torch.equal(run64, 2.0 * acc.reshape(-1).double())
     plan.close()
+
+
+@pytest.mark.parametrize("T,F,N", [(64, 5, 36), (96, 3, 100), (128, 2, 200), (40, 9, 64)])
+def test_fused_running_sum_equals_accumulate_then_dump(T, F, N):
+    """bfx_xengine_accumulate_run64 over three gulps gives the same bits as
+    accumulate (overwrite) followed by dump into a running sum, for both
+    kernel variants, on packed one-block arrays and ragged multi-block ones."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    banner(f"xengine cf16 fused running sum T={T} F={F} N={N}")
+    plan = bfx.bfx_xengine_create(N, F, "cf16")
+    P = N * (N + 1) // 2
+    xs = [to_dev(synth.cf16_voltages(90 + k + N, T, F, N)) for k in range(3)]
+    for v in range(bfx.bfx_xengine_num_variants(plan)):
+        bfx.bfx_xengine_set_variant(plan, v)
+        acc = bfx.visibilities_buffer(plan)
+        two_step = torch.zeros(F * P * 2, dtype=torch.float64, device="cuda")
+        fused = torch.full((F * P * 2,), 0.0, dtype=torch.float64, device="cuda")
+        for x in xs:
+            bfx.bfx_xengine_accumulate(plan, x, T, acc, overwrite=True)
+            bfx.bfx_xengine_dump(plan, acc, None, two_step)
+            bfx.bfx_xengine_accumulate_run64(plan, x, T, fused)
+        torch.cuda.synchronize()
+        assert torch.equal(fused, two_step), f"variant {v}"
+        assert bool(torch.isfinite(fused).all())
+    plan.close()
