@@ -83,10 +83,26 @@ __device__ __forceinline__ int pass3_butterfly(int tid) {
 
 __device__ float2 g_twiddle[kN];  // exp(-2 pi i m / 4096), m = 0..4095
 
-__device__ __forceinline__ int8_t requant(float v, float s) {
-    float r = rintf(s * v);  // round half to even
-    r = fminf(fmaxf(r, -127.0f), 127.0f);
-    return (int8_t)r;
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// Requantize: round half to even of v s, saturated to +-127, returned as the
+// low byte of a binary32 bit pattern.  fma(v, s, 1.5 2^23) rounds the exact
+// product to an integer n once (|v s| < 2^22 keeps the sum in [2^23, 2^24),
+// where the spacing is 1, and 1.5 2^23 is even, so ties go to even n) and
+// leaves 1.5 2^23 + n, whose bit pattern is 0x4B400000 + n; clamping that
+// float to 1.5 2^23 +- 127 saturates n, and every |v s| >= 2^22 lands
+// outside the clamp range on the correct side.
+__device__ __forceinline__ uint32_t requant_bits(float v, float s) {
+    constexpr float kMagic = 12582912.0f;
+    const float t = __builtin_fmaf(v, s, kMagic);
+    return __float_as_uint(__builtin_amdgcn_fmed3f(t, kMagic - 127.0f, kMagic + 127.0f));
+}
+
+// Low bytes of four words as one word, r0 in byte 0.
+__device__ __forceinline__ uint32_t pack_low_bytes(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3) {
+    const uint32_t lo = __builtin_amdgcn_perm(r1, r0, 0x0c0c0400u);
+    const uint32_t hi = __builtin_amdgcn_perm(r3, r2, 0x0c0c0400u);
+    return lo | (hi << 16);
 }
 
 // Work item B -> (frame s, input group g); frames map to XCDs by s % 8.
@@ -98,12 +114,38 @@ __device__ __forceinline__ bool item_of(int B, int ngroup, int nspec, int &s, in
     return s < nspec;
 }
 
-// The 16 first-pass rows (j + 256 r) of this lane for the item's 8 inputs.
+// Sample loads: raw buffer access, a uniform base in a buffer descriptor
+// (scalar registers) plus a lane's 32-bit offset and a uniform 32-bit offset.
+// A frame spans fewer than 2^32 bytes, so per-lane addresses need no 64-bit
+// vector arithmetic.  Descriptor word 3: 32-bit data format (required by gfx9
+// for raw buffer access); no range is enforced below 2^32.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const void *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xFFFFFFFFu, 0x00020000);
+}
+
+// Output stores go through global (not buffer) stores: the same kind of
+// uniform base, kept whole in scalar registers, plus the lane's 32-bit offset.
+// (A 16-byte buffer store with a scalar offset register gets no wait state
+// before its data registers are overwritten, and its first dword was seen to
+// take the overwriting value.)
+#define BFX_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ BFX_GLOBAL T *uniform_ptr(T *p) {
+    uint64_t u = (uint64_t)p;
+    asm volatile("" : "+s"(u));
+    return (BFX_GLOBAL T *)u;
+}
+
+// The 16 first-pass rows (j + 256 r) of this lane for the item's 8 inputs,
+// joff = j ninput.
 __device__ __forceinline__ void load_samples(uint64_t (&x)[16], const int8_t *in, int ninput, int s,
-                                             int g, int j) {
-    const int8_t *src = in + ((int64_t)s * kN + j) * ninput + g * kGroup;
+                                             int g, uint32_t joff) {
+    const __amdgpu_buffer_rsrc_t rs = frame_rsrc(in + (int64_t)s * kN * ninput + g * kGroup);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = *(const uint64_t *)(src + (int64_t)(256 * r) * ninput);
+    for (int r = 0; r < 16; ++r) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, joff, 256 * r * ninput, 0);
+        x[r] = (uint64_t)(uint32_t)w[0] | ((uint64_t)(uint32_t)w[1] << 32);
+    }
 }
 
 template <bool CI8>
@@ -123,8 +165,12 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
 
     // twiddles of this lane's pass-2 (Ns = 16) and pass-3 (Ns = 256) butterflies
     const int b3 = pass3_butterfly(j);
-    const bool self0 = b3 == 0, self128 = b3 == 128;  // self-paired butterflies
-    const bool lower = (j & 63) < 32;
+    const bool self0 = b3 == 0;  // butterflies 0 and 128 pair with themselves
+    // Z[-k] of butterfly b3 lives in the lane holding 256 - b3: lane j ^ 32,
+    // except for the self-paired butterflies (lanes 0 and 32 of wave 0), which
+    // read their own registers (ds_bpermute byte address of the source lane)
+    const int partner = (b3 == 0 || b3 == 128) ? (j & 63) : ((j & 63) ^ 32);
+    const int paddr = 4 * partner;
     // pass-3 twiddles in registers; the pass-2 ones (16 distinct sets, by
     // j % 16) in a small LDS table, published by the first barrier
     float2 tw3[16];
@@ -132,10 +178,22 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
     for (int r = 0; r < 16; ++r) tw3[r] = g_twiddle[(r * b3) & (kN - 1)];
     float2 *tw2 = (float2 *)(lds + kABytes + kBBytes);
     tw2[j] = g_twiddle[((j >> 4) * (j & 15) * (kN / 256)) & (kN - 1)];  // entry 16 r + c
-    // a row's 8 bytes (the item's 8 inputs); each pair takes the low 16 bits
-    // and shifts them out, so the pair loop never selects by its index
+    // scale of channel b3 + 256 c, halved (the split's 1/2 rides on it:
+    // fl(s fl(x / 2)) = fl((s / 2) x))
+    float hs[kChan / kThreads];
+    if (CI8) {
+#pragma unroll
+        for (int c = 0; c < kChan / kThreads; ++c) hs[c] = 0.5f * scale[b3 + kThreads * c];
+    }
+    // 32-bit per-lane offsets within a frame (a frame spans < 2^32 bytes)
+    const uint32_t joff = (uint32_t)(j * ninput);
+    const uint32_t koff = (uint32_t)(b3 * ninput) * (CI8 ? 2u : 8u);  // channel b3's row
+    const uint32_t cstride = (uint32_t)(kThreads * ninput) * (CI8 ? 2u : 8u);  // 256 channels
+    // a row's 8 bytes (the item's 8 inputs); pair p takes bytes 2 p, 2 p + 1
+    // with one v_perm whose selector is uniform, so the pair loop never
+    // selects registers by its index
     uint64_t xs[16];
-    load_samples(xs, in, ninput, s, g, j);
+    load_samples(xs, in, ninput, s, g, joff);
 
     while (true) {
         // next item: its samples are fetched into the registers of this
@@ -145,6 +203,8 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
         bool nvalid = false;
         while (Bn < total_flat && !(nvalid = item_of(Bn, ngroup, nspec, sn, gn))) Bn += gridDim.x;
         const int i0 = g * kGroup;
+        // frame s, input i0 of the output (uniform); channel rows add koff
+        uint8_t *orow = (uint8_t *)out + ((int64_t)s * kChan * ninput + i0) * (CI8 ? 2 : 8);
 
         // ci8 bytes (a_re, a_im, b_re, b_im) of each pair, rotated in pair by
         // pair so that after the last pair q[c] holds pairs 0..3 in order
@@ -156,18 +216,21 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
         // pair.
         float2 *A = buf0;
         float2 *Bf = buf1;
-        // (not unrolled: one pair's registers at a time)
-#pragma unroll 1
-        for (int p = 0; p < kPairs; ++p) {
+        // One pair's transform.  Pairs 0..2 run in a loop (not unrolled: one
+        // pair's registers at a time); the last pair, peeled, also fetches the
+        // next item's samples once its own are taken, so within the loop the
+        // sample registers never change.
+        auto pair = [&](const int p, const bool prefetch) {
             // pass 1 (Ns = 1): z[n] = x_a[n] + i x_b[n], n = j + 256 r
             float2 v[16];
+            // bytes 2 p, 2 p + 1 of a row word to bytes 0, 1 (v_perm selector)
+            const uint32_t sel = 0x0c0c0000u | (uint32_t)(2 * p) | ((uint32_t)(2 * p + 1) << 8);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint32_t two = (uint32_t)xs[r];  // bytes 2 p, 2 p + 1 of the row
-                xs[r] >>= 16;
+                const uint32_t two = __builtin_amdgcn_perm((uint32_t)(xs[r] >> 32), (uint32_t)xs[r], sel);
                 v[r] = float2{(float)(int8_t)(two & 0xFF), (float)(int8_t)((two >> 8) & 0xFF)};
             }
-            if (p == kPairs - 1 && nvalid) load_samples(xs, in, ninput, sn, gn, j);
+            if (prefetch) load_samples(xs, in, ninput, sn, gn, joff);
             dft16(v);
 #pragma unroll
             for (int r = 0; r < 16; ++r) A[pad_a(16 * j + r)] = v[r];
@@ -194,45 +257,48 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
             dft16(v);
             // two-for-one split for k = b3 + 256 m, m = 0..7:
             // Z[-k] = register 15 - m of butterfly 256 - b3, 32 lanes away
-            // (one v_permlane32_swap per component); butterfly 0 uses its own
-            // register (16 - m) % 16, butterfly 128 its own register 15 - m
+            // (a ds_bpermute per component: a wavefront shuffle through the
+            // LDS crossbar, no LDS storage and no barrier); butterfly 128
+            // reads its own register 15 - m, butterfly 0 its own register
+            // (16 - m) % 16
+            float2 wv[kChan / kThreads];
 #pragma unroll
             for (int c = 0; c < kChan / kThreads; ++c) {
-                const int k = b3 + kThreads * c;
+                wv[c].x = __int_as_float(__builtin_amdgcn_ds_bpermute(paddr, __float_as_int(v[15 - c].x)));
+                wv[c].y = __int_as_float(__builtin_amdgcn_ds_bpermute(paddr, __float_as_int(v[15 - c].y)));
+            }
+            if (self0) {
+#pragma unroll
+                for (int c = 0; c < kChan / kThreads; ++c) wv[c] = v[(16 - c) & 15];
+            }
+#pragma unroll
+            for (int c = 0; c < kChan / kThreads; ++c) {
                 const float2 z = v[c];
-                const auto sx = __builtin_amdgcn_permlane32_swap(__float_as_int(v[15 - c].x),
-                                                                  __float_as_int(v[15 - c].x), false, false);
-                const auto sy = __builtin_amdgcn_permlane32_swap(__float_as_int(v[15 - c].y),
-                                                                  __float_as_int(v[15 - c].y), false, false);
-                float2 w{__int_as_float(lower ? sx[1] : sx[0]), __int_as_float(lower ? sy[1] : sy[0])};
-                if (self128) w = v[15 - c];
-                if (self0) w = v[(16 - c) & 15];
+                const float2 w = wv[c];
                 // X_a = (z + conj w)/2, X_b = (z - conj w)/(2i) = -i (z - conj w)/2
                 if (CI8) {
-                    // the halving rides on the scale: fl(s fl(x / 2)) = fl((s / 2) x)
-                    const float hs = 0.5f * scale[k];
-                    const uint32_t word = (uint32_t)(uint8_t)requant(z.x + w.x, hs) |
-                                          ((uint32_t)(uint8_t)requant(z.y - w.y, hs) << 8) |
-                                          ((uint32_t)(uint8_t)requant(z.y + w.y, hs) << 16) |
-                                          ((uint32_t)(uint8_t)requant(w.x - z.x, hs) << 24);
+                    const uint32_t word = pack_low_bytes(requant_bits(z.x + w.x, hs[c]),
+                                                         requant_bits(z.y - w.y, hs[c]),
+                                                         requant_bits(z.y + w.y, hs[c]),
+                                                         requant_bits(w.x - z.x, hs[c]));
                     q[c] = uint4{q[c].y, q[c].z, q[c].w, word};
                 } else {
                     const float2 xa{0.5f * (z.x + w.x), 0.5f * (z.y - w.y)};
                     const float2 xb{0.5f * (z.y + w.y), -0.5f * (z.x - w.x)};
-                    float4 *o = (float4 *)((float *)out +
-                                           (((int64_t)s * kChan + k) * ninput + i0 + 2 * p) * 2);
-                    *o = float4{xa.x, xa.y, xb.x, xb.y};
+                    *(BFX_GLOBAL v4u *)(uniform_ptr(orow + 16 * p + c * cstride) + koff) =
+                        v4u{__float_as_uint(xa.x), __float_as_uint(xa.y), __float_as_uint(xb.x),
+                            __float_as_uint(xb.y)};
                 }
             }
-        }
+        };
+#pragma unroll 1
+        for (int p = 0; p < kPairs - 1; ++p) pair(p, false);
+        pair(kPairs - 1, nvalid);
         if (CI8) {
             // [k][8 inputs][re, im] = the 4 pairs' bytes in order: 16 bytes
-            int8_t *o = (int8_t *)out;
 #pragma unroll
-            for (int c = 0; c < kChan / kThreads; ++c) {
-                const int k = b3 + kThreads * c;
-                *(uint4 *)(o + (((int64_t)s * kChan + k) * ninput + i0) * 2) = q[c];
-            }
+            for (int c = 0; c < kChan / kThreads; ++c)
+                *(BFX_GLOBAL v4u *)(uniform_ptr(orow + c * cstride) + koff) = v4u{q[c].x, q[c].y, q[c].z, q[c].w};
         }
         if (!nvalid) break;
         B = Bn;
