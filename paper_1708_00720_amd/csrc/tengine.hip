@@ -11,7 +11,9 @@
 // computed in binary32.
 //
 // The shift multiplies the inverse transform by exp(-i pi n) = (-1)^n.  The
-// inverse transform is taken as conj(FFT(conj X)) with the forward radix-16
+// inverse transform is taken as swap(FFT(swap X)), swap(a + ib) = b + ia
+// (= i conj(a + ib), so swap(FFT(swap X)) = conj(FFT(conj X)) = N IFFT(X);
+// the swaps are register renamings, no arithmetic), with the forward radix-16
 // Stockham machinery of the F-engine: 4096 = 16^3, 256 lanes with 16 points
 // each, three passes.  The third pass leaves output n = j + 256 r in lane j's
 // register r, so the shift, the mixer and the quantization run in registers
@@ -53,9 +55,39 @@ __device__ __forceinline__ bool item_of(int B, int ngroup, int nspec, int &s, in
     return s < nspec;
 }
 
-__device__ __forceinline__ int quant(float v, float lim) {
-    return (int)fminf(fmaxf(rintf(v), -lim), lim);  // round half to even
+// Quantize: round half to even, saturated to +-lim, returned as the low bits
+// of a binary32 bit pattern.  v + 1.5 2^23 rounds v to an integer n once
+// (|v| < 2^22 keeps the sum in [2^23, 2^24), where the spacing is 1, and
+// 1.5 2^23 is even, so ties go to even n) and leaves 1.5 2^23 + n, whose bit
+// pattern is 0x4B400000 + n; clamping that float to 1.5 2^23 +- lim
+// saturates n, and every |v| >= 2^22 lands outside the clamp range on the
+// correct side.  The low byte is n as int8, the low nibble n as int4.
+__device__ __forceinline__ uint32_t quant_bits(float v, float lim) {
+    constexpr float kMagic = 12582912.0f;
+    return __float_as_uint(__builtin_amdgcn_fmed3f(v + kMagic, kMagic - lim, kMagic + lim));
 }
+
+// Sample loads: raw buffer access, a uniform base in a buffer descriptor
+// (scalar registers) plus a lane's 32-bit offset and a uniform 32-bit offset.
+// Descriptor word 3: 32-bit data format (required by gfx9 for raw buffer
+// access); no range is enforced below 2^32.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const void *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xFFFFFFFFu, 0x00020000);
+}
+
+// Output stores go through global (not buffer) stores: a uniform base kept
+// whole in scalar registers plus the lane's 32-bit offset.  (A 16-byte buffer
+// store with a scalar offset register gets no wait state before its data
+// registers are overwritten.)
+#define BFX_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ BFX_GLOBAL T *uniform_ptr(T *p) {
+    uint64_t u = (uint64_t)p;
+    asm volatile("" : "+s"(u));
+    return (BFX_GLOBAL T *)u;
+}
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 // Mixer factors shared by every lane: output n = j + 256 r of a frame has
 // phase index m(j) + r * ((256 mix_num) mod mix_den), so its phasor is the
@@ -88,6 +120,10 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
     // output n = j + 256 r has the shift sign (-1)^j; the sign, 1/nfft and the
     // scale ride on the lane's mixer phasor
     const float sgn_scale = ((j & 1) ? -inv_n : inv_n) * scale;
+    // 32-bit per-lane offsets within a frame (a frame spans < 2^32 bytes of
+    // input and of output): input row j of the band, output row j
+    const uint32_t joff = (uint32_t)(j * ninput) * 2u;
+    const uint32_t ooff = (uint32_t)(j * ninput) * (CI4 ? 1u : 2u);
 
     for (int B = blockIdx.x; B < total_flat; B += gridDim.x) {
         int s, g;
@@ -95,9 +131,13 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
         const int i0 = g * kGroup;
         uint4 xs[16];
         {
-            const int8_t *src = in + (((int64_t)s * nchan + chan0 + j) * ninput + i0) * 2;
+            // frame s, channel chan0, input i0 (uniform); rows j + 256 r
+            const __amdgpu_buffer_rsrc_t rs = frame_rsrc(in + (((int64_t)s * nchan + chan0) * ninput + i0) * 2);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) xs[r] = *(const uint4 *)(src + (int64_t)(256 * r) * ninput * 2);
+            for (int r = 0; r < 16; ++r) {
+                const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, joff, 256 * r * ninput * 2, 0);
+                xs[r] = uint4{(uint32_t)w[0], (uint32_t)w[1], (uint32_t)w[2], (uint32_t)w[3]};
+            }
         }
         // mixer phasor of this lane's output t = s N + j (exact phase index),
         // times the shift sign, 1/nfft and the scale
@@ -118,8 +158,8 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
             for (int r = 0; r < 16; ++r) {
                 const uint32_t w = ii < 2 ? xs[r].x : ii < 4 ? xs[r].y : ii < 6 ? xs[r].z : xs[r].w;
                 const uint32_t two = w >> (16 * (ii & 1));
-                // conj(X): the inverse transform as conj(FFT(conj X))
-                v[r] = float2{(float)(int8_t)(two & 0xFF), -(float)(int8_t)((two >> 8) & 0xFF)};
+                // swap(X): the inverse transform as swap(FFT(swap X))
+                v[r] = float2{(float)(int8_t)((two >> 8) & 0xFF), (float)(int8_t)(two & 0xFF)};
             }
             dft16(v);
 #pragma unroll
@@ -143,35 +183,42 @@ __global__ __launch_bounds__(kThreads, 2) void tengine_kernel(
                 v[r] = r == 0 ? x : cmul(x, tw3[r]);
             }
             dft16(v);
-            // v[r] = FFT(conj X)[n], n = j + 256 r:  z = conj(v) (-1)^n / N, and
-            // scale z e^{i phase} = conj(v) w with w = E_r ph0 (sign, 1/N, scale in
+            // v[r] = FFT(swap X)[n], n = j + 256 r:  z = swap(v) (-1)^n / N, and
+            // scale z e^{i phase} = swap(v) w with w = E_r ph0 (sign, 1/N, scale in
             // ph0).  w is formed anew for each input: hoisted out of the input
             // loop, its 16 values would take 32 more registers than there are.
             asm volatile("" : "+v"(ph0.x), "+v"(ph0.y));
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float2 w = cmul(E.e[r], ph0);
-                const float2 zm{v[r].x * w.x + v[r].y * w.y, v[r].x * w.y - v[r].y * w.x};
-                const int qr = quant(zm.x, lim), qi = quant(zm.y, lim);
+                const float2 zm{v[r].y * w.x - v[r].x * w.y, v[r].y * w.y + v[r].x * w.x};
+                const uint32_t qr = quant_bits(zm.x, lim), qi = quant_bits(zm.y, lim);
                 if (CI4) {
-                    const uint32_t b = (((uint32_t)qr & 15u) << 4) | ((uint32_t)qi & 15u);
-                    const int w = ii >> 2, sh = 8 * (ii & 3);
-                    code[r][w] = (ii & 3) == 0 ? b : (code[r][w] | (b << sh));
+                    // byte (re << 4) | im of input ii into byte ii % 4 of word
+                    // ii / 4 (v_perm: bytes below from the word, the new byte
+                    // from b, bytes above cleared)
+                    const uint32_t b = (qr << 4) | (qi & 15u);
+                    constexpr uint32_t kIns[4] = {0x0c0c0c04u, 0x0c0c0400u, 0x0c040100u, 0x04020100u};
+                    const int w = ii >> 2;
+                    code[r][w] = __builtin_amdgcn_perm(b, (ii & 3) == 0 ? 0u : code[r][w], kIns[ii & 3]);
                 } else {
-                    const uint32_t h = ((uint32_t)qr & 0xFFu) | (((uint32_t)qi & 0xFFu) << 8);
-                    const int w = ii >> 1, sh = 16 * (ii & 1);
-                    code[r][w] = (ii & 1) == 0 ? h : (code[r][w] | (h << sh));
+                    // (re, im) bytes of input ii into half ii % 2 of word ii / 2
+                    const uint32_t h = __builtin_amdgcn_perm(qi, qr, 0x0c0c0400u);
+                    const int w = ii >> 1;
+                    code[r][w] = (ii & 1) == 0 ? h : __builtin_amdgcn_perm(h, code[r][w], 0x05040100u);
                 }
             }
         }
         // rows t = s N + j + 256 r, the item's 8 inputs
+        uint8_t *orow = out + ((int64_t)s * kN * ninput + i0) * (CI4 ? 1 : 2);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t t = (int64_t)s * kN + j + 256 * r;
+            const uint32_t roff = (uint32_t)(256 * r * ninput) * (CI4 ? 1u : 2u);
             if (CI4) {
-                *(uint2 *)(out + t * ninput + i0) = uint2{code[r][0], code[r][1]};
+                *(BFX_GLOBAL v2u *)(uniform_ptr(orow + roff) + ooff) = v2u{code[r][0], code[r][1]};
             } else {
-                *(uint4 *)(out + (t * ninput + i0) * 2) = uint4{code[r][0], code[r][1], code[r][2], code[r][3]};
+                *(BFX_GLOBAL v4u *)(uniform_ptr(orow + roff) + ooff) =
+                    v4u{code[r][0], code[r][1], code[r][2], code[r][3]};
             }
         }
     }
