@@ -27,8 +27,9 @@
 // butterfly b in lane i < 32 and 256 - b in lane i + 32 (wave 0 keeps the
 // self-paired 0 and 128 in lanes 0 and 32).  Butterfly b holds Z[b + 256 m],
 // and Z[-k] for k = b + 256 m is register 15 - m of butterfly 256 - b, so the
-// split needs one v_permlane32_swap per register -- a wavefront shuffle, no
-// LDS and no barrier.  The third pass reads butterflies above 128 in reversed
+// split needs one ds_bpermute per register component from the lane 32 away --
+// a wavefront shuffle through the LDS crossbar, no LDS storage and no
+// barrier.  The third pass reads butterflies above 128 in reversed
 // order in a buffer laid out to match (index map piB), so both half-waves read
 // ascending addresses.
 //
@@ -61,8 +62,7 @@ constexpr int kPairs = kGroup / 2; // complex sequences per workgroup
 constexpr int kThreads = 256;      // lanes of one FFT (4096 / 16 points each)
 constexpr int kABytes = kPadAElems * 8;             // pass 1 -> 2, padded (pad_a)
 constexpr int kBBytes = kN * 8;                     // pass 2 -> 3, swizzled (swz_b)
-constexpr int kTw2Bytes = 256 * 8;                  // pass-2 twiddles W^(16 r c), r, c < 16
-constexpr int kLdsBytes = kABytes + kBBytes + kTw2Bytes;  // two workgroups per CU
+constexpr int kLdsBytes = kABytes + kBBytes;      // two workgroups per CU
 
 // Buffer A (pass 1 -> 2) uses the additive pad_a (fft16.h).
 // Buffer B (pass 2 -> 3): butterflies above 128 of each 256 block in reversed
@@ -171,13 +171,14 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
     // read their own registers (ds_bpermute byte address of the source lane)
     const int partner = (b3 == 0 || b3 == 128) ? (j & 63) : ((j & 63) ^ 32);
     const int paddr = 4 * partner;
-    // pass-3 twiddles in registers; the pass-2 ones (16 distinct sets, by
-    // j % 16) in a small LDS table, published by the first barrier
-    float2 tw3[16];
+    // pass-2 (W^(16 r (j % 16))) and pass-3 (W^(r b3)) twiddles in registers
+    // (holding the pass-2 ones in an LDS table instead was 2.5% slower)
+    float2 tw2[16], tw3[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) tw3[r] = g_twiddle[(r * b3) & (kN - 1)];
-    float2 *tw2 = (float2 *)(lds + kABytes + kBBytes);
-    tw2[j] = g_twiddle[((j >> 4) * (j & 15) * (kN / 256)) & (kN - 1)];  // entry 16 r + c
+    for (int r = 0; r < 16; ++r) {
+        tw2[r] = g_twiddle[(r * (j & 15) * (kN / 256)) & (kN - 1)];
+        tw3[r] = g_twiddle[(r * b3) & (kN - 1)];
+    }
     // scale of channel b3 + 256 c, halved (the split's 1/2 rides on it:
     // fl(s fl(x / 2)) = fl((s / 2) x))
     float hs[kChan / kThreads];
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(kThreads, 2) void fengine_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float2 x = A[pad_a(j + 256 * r)];
-                v[r] = r == 0 ? x : cmul(x, tw2[16 * r + (j & 15)]);
+                v[r] = r == 0 ? x : cmul(x, tw2[r]);
             }
             dft16(v);
             {
