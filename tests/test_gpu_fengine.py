@@ -223,3 +223,50 @@ def test_fx_chain_tone_closed_form(fx_full):
     est = slope + np.sum(resid * dt) / np.sum(dt * dt)
     print(f"fitted phase slope {est:.5f} rad/sample (model {slope:.5f})")
     assert abs(est / slope - 1) < 0.01
+
+
+def test_most_inputs_sampled():
+    """65536 inputs (the largest accepted) and 17 frames: the input passes 2^32
+    bytes (frame 16 starts at 4.3 GB) and a frame spans 2^28 bytes, so the
+    kernel's 32-bit lane, row and channel offsets reach their largest values.
+    Uniform codes over the whole int8 range (-128 included).  Binary32
+    spectra of 12 sampled inputs (both ends of the range, group edges) in
+    frames 0 and 16 against the double DFT, then their ci8 codes against the
+    oracle's requantizer (near-ties flagged a priori)."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    ninput, nspec = 65536, 17
+    frames = (0, 16)
+    inputs = [0, 1, 7, 8, 4095, 4096, 32767, 32768, 65527, 65528, 65534, 65535]
+    banner(f"fengine cf32 + ci8 ninput={ninput} nspec={nspec}")
+    gen = torch.Generator(device="cuda").manual_seed(43)
+    d_in = torch.randint(-128, 128, (nspec * NFFT * ninput,), dtype=torch.int8, device="cuda", generator=gen)
+    rows = d_in.view(nspec * NFFT, ninput)
+    idx = torch.tensor(inputs, device="cuda")
+    # the sampled columns of the sampled frames, as a compact 2-frame array
+    xc = np.concatenate([rows[s * NFFT:(s + 1) * NFFT].index_select(1, idx).cpu().numpy() for s in frames])
+    fidx = torch.tensor(frames, device="cuda")
+
+    out = torch.zeros(nspec * NCHAN * ninput * 2, dtype=torch.float32, device="cuda")
+    bfx.bfx_fengine(d_in, ninput, NFFT, nspec, torch.ones(NCHAN, device="cuda"), out, out="cf32")
+    torch.cuda.synchronize()
+    got = out.view(nspec, NCHAN, ninput, 2).index_select(0, fidx).index_select(2, idx).cpu().numpy()
+    del out
+    want = _oracle_spectrum(xc, len(inputs), range(len(frames)), list(range(len(inputs))))
+    worst = 0.0
+    for (s, i), w in want.items():
+        g = got[s, :, i, 0].astype(np.float64) + 1j * got[s, :, i, 1]
+        worst = max(worst, _normwise(g, w))
+    print(f"worst normwise relative error {worst:.3e}")
+    assert worst <= 1e-6
+
+    scale = synth.fengine_scale(NCHAN)
+    out = torch.zeros(nspec * NCHAN * ninput * 2, dtype=torch.int8, device="cuda")
+    bfx.bfx_fengine(d_in, ninput, NFFT, nspec, torch.from_numpy(np.asarray(scale, np.float32)).cuda(), out,
+                    out="ci8")
+    torch.cuda.synchronize()
+    gotq = out.view(nspec, NCHAN, ninput, 2).index_select(0, fidx).index_select(2, idx).cpu().numpy()
+    del out, d_in
+    total, nflag, nmiss = _check_ci8_codes(xc, gotq, scale, range(len(frames)), list(range(len(inputs))))
+    print(f"{total} codes, {nflag} inside the tie window, {nmiss} differ by one")
+    assert gotq.min() >= -127

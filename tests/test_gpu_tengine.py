@@ -37,14 +37,17 @@ def _run(x, nchan, ninput, nspec, chan0, mix_num, mix_den, scale, out):
     return re, im
 
 
-def _check(x, gre, gim, chan0, mix_num, mix_den, scale, out, frames, inputs):
+def _check(x, gre, gim, chan0, mix_num, mix_den, scale, out, frames, inputs, run_frames=None):
     """Compare the GPU codes of (frames x inputs) with the oracle's.  The
     oracle runs on each listed frame alone, which gives its mixer the time
     index n instead of s * nfft + n: the caller lists frames s with
-    mix_num * s * nfft = 0 (mod mix_den), where the two phases agree."""
+    mix_num * s * nfft = 0 (mod mix_den), where the two phases agree.  When
+    x and the codes hold only some frames of the run, run_frames gives each
+    listed frame's index in the run (for that condition)."""
     nflag = ndiff = total = 0
-    for s in frames:
-        assert (mix_num * s * NFFT) % mix_den == 0
+    for k, s in enumerate(frames):
+        rs = s if run_frames is None else run_frames[k]
+        assert (mix_num * rs * NFFT) % mix_den == 0
         sub = np.ascontiguousarray(x[s:s + 1][:, :, inputs])
         q, z = oracle.tengine(sub, chan0, NFFT, mix_num, mix_den, scale,
                               out_bits=8 if out == "ci8" else 4, want_z=True)
@@ -125,4 +128,35 @@ def test_largest_mixer_denominator():
     x = synth.voltages(14, nspec, nchan, ninput, "ci8", 8.0, 127)
     gre, gim = _run(x, nchan, ninput, nspec, chan0, mix_num, mix_den, scale, "ci8")
     total, nflag, ndiff = _check(x, gre, gim, chan0, mix_num, mix_den, scale, "ci8", (0,), list(range(ninput)))
+    print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one")
+
+
+def test_most_inputs_sampled():
+    """65536 inputs (the largest accepted), 9 frames of 4096 channels: the
+    input passes 2^32 bytes (frame 8 starts at 4.3 GB) and a frame's band
+    spans 2^29 bytes, so the kernel's 32-bit lane and row offsets reach their
+    largest values.  Uniform codes over the whole int8 range, 4+4 output,
+    mixer 1/4 channel (period 4 frames); 12 sampled inputs of frames 0 and 8
+    against the oracle."""
+    import torch
+    import paper_1708_00720_amd as bfx
+    nspec, nchan, ninput, chan0 = 9, NFFT, 65536, 0
+    mix_num, mix_den, scale = 1, 4 * NFFT, 2.0
+    frames = (0, 8)
+    inputs = [0, 1, 7, 8, 4095, 4096, 32767, 32768, 65527, 65528, 65534, 65535]
+    banner(f"tengine ci4 ninput={ninput} nspec={nspec}")
+    gen = torch.Generator(device="cuda").manual_seed(15)
+    d_in = torch.randint(-128, 128, (nspec * nchan * ninput * 2,), dtype=torch.int8, device="cuda", generator=gen)
+    idx = torch.tensor(inputs, device="cuda")
+    fidx = torch.tensor(frames, device="cuda")
+    x = d_in.view(nspec, nchan, ninput, 2).index_select(0, fidx).index_select(2, idx).cpu().numpy()
+    d_out = torch.full((nspec * NFFT * ninput,), 0x55, dtype=torch.uint8, device="cuda")
+    bfx.bfx_tengine(d_in, nchan, ninput, nspec, chan0, NFFT, mix_num, mix_den, scale, d_out, out="ci4")
+    torch.cuda.synchronize()
+    h = d_out.view(nspec, NFFT, ninput).index_select(0, fidx).index_select(2, idx).cpu().numpy()
+    del d_in, d_out
+    gre, gim = oracle.unpack_ci4(h.reshape(len(frames) * NFFT, len(inputs)))
+    # compact frame c is frame frames[c] of the run
+    total, nflag, ndiff = _check(x, gre, gim, chan0, mix_num, mix_den, scale, "ci4", range(len(frames)),
+                                 list(range(len(inputs))), run_frames=frames)
     print(f"{total} codes, {nflag} in the tie window, {ndiff} differ by one")
