@@ -1,6 +1,6 @@
 // Radix-16 building blocks of the FFT kernels (F-engine and T-engine):
 // complex multiply, forward 4- and 16-point DFTs in registers, the padded
-// LDS indices of the Stockham exchanges and a fence-free workgroup barrier.
+// LDS indices of the Stockham exchanges and the exchanges' workgroup barrier.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -69,8 +69,14 @@ __device__ __forceinline__ void dft16(float2 (&v)[16]) {
     for (int k = 0; k < 16; ++k) v[k] = t[k];
 }
 
+// Workgroup barrier of an LDS exchange: the wave's LDS writes are complete
+// (lgkmcnt = 0; vmcnt and expcnt left at their maxima) before it arrives, so
+// every wave past the barrier reads them.  gfx950 does not wait for
+// outstanding memory operations at s_barrier by itself, and no release fence
+// is needed beyond that (the exchange is LDS only).
 __device__ __forceinline__ void block_barrier() {
     asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }

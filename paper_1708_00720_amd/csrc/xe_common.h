@@ -44,7 +44,11 @@ constexpr int kRingBytes = kRing * kStageBytes;
 // The ring plus 1 KiB that receives the dummy DMA of a chunk fetched by the
 // synchronous path (keeps every stage at exactly its DMA operation count
 // per wave, which the vmcnt waits count on).
-constexpr int kLdsBytes = kRingBytes + 1024;
+// Then the task table of a single array's items (see SingleArray): 8 bytes
+// per item, at most tri_items(128) items (8192 inputs).
+constexpr int kTaskTabEntries = 2080;
+constexpr int kTaskTabOff = kRingBytes + 1024;
+constexpr int kLdsBytes = kTaskTabOff + kTaskTabEntries * 8;
 // Each of NW DMA waves issues an equal share of each stage's DMA
 // (16-byte-per-lane instructions, 1 KiB each).
 template <int NW>
@@ -115,6 +119,28 @@ __device__ inline void decode_item(int nb, int item, Task &tk) {
             if (k < h) { tk.blk[w + 1] = 2 * k + 1; tk.rs[w] = 0; tk.cs[w] = w + 1; }
         }
         if (g == 0) { tk.rs[3] = 0; tk.cs[3] = 0; }
+    }
+}
+
+// Compact form of a triangle item's task (every slot in channel 0): the input
+// block of each slot as a signed byte, and the row and column slot of each
+// pair as 4-bit two's-complement fields (-1 = unused).
+__device__ inline uint2 pack_task(const Task &tk) {
+    uint32_t b = 0, s = 0;
+    for (int k = 0; k < 4; ++k) {
+        b |= (uint32_t)(tk.blk[k] & 0xFF) << (8 * k);
+        s |= ((uint32_t)(tk.rs[k] & 15) << (4 * k)) | ((uint32_t)(tk.cs[k] & 15) << (16 + 4 * k));
+    }
+    return uint2{b, s};
+}
+
+__device__ __forceinline__ void unpack_task(uint32_t b, uint32_t s, Task &tk) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        tk.blk[k] = (int)(b << (24 - 8 * k)) >> 24;
+        tk.rs[k] = (int)(s << (28 - 4 * k)) >> 28;
+        tk.cs[k] = (int)(s << (12 - 4 * k)) >> 28;
+        tk.chan[k] = 0;
     }
 }
 
@@ -252,12 +278,39 @@ __device__ inline void decode_task(const Item &it, Task &tk) {
     else decode_item(it.nb, it.item, tk);
 }
 
+// The task of an item, from the work source's table in LDS when it keeps one
+// (a wave-uniform LDS read instead of the closed-form decode).
+template <class W>
+__device__ __forceinline__ void task_of(const Item &it, const uint2 *tab, Task &tk) {
+    if constexpr (W::kTable) {
+        if (it.npack) {
+            decode_packed(it.npack, tk);
+        } else {
+            const uint2 e = tab[it.item];
+            unpack_task(__builtin_amdgcn_readfirstlane(e.x), __builtin_amdgcn_readfirstlane(e.y), tk);
+        }
+    } else {
+        decode_task(it, tk);
+    }
+}
+
 // Work source of a single array.  Flat id B maps to channel group g with
 // B % 8 == g % 8, so with round-robin dispatch over the 8 XCDs all items of a
 // channel run on one XCD and share its L2.  A group is one channel, or four
 // channels packed into one item when the array has a single input block.
 // Padding ids of a group count that is not a multiple of 8 return false.
 struct SingleArray {
+    // The tasks of a channel's items are decoded once per workgroup into an
+    // LDS table (a one-block array's packed items need none).
+    static constexpr bool kTable = true;
+    __device__ __forceinline__ void fill_table(uint2 *tab, int tid, int nthreads) const {
+        if (npk > 1) return;
+        for (int i = tid; i < nitems; i += nthreads) {
+            Task tk;
+            decode_item(nb, i, tk);
+            tab[i] = pack_task(tk);
+        }
+    }
     const uint8_t *in;
     void *out;
     int64_t t_stride;
@@ -311,10 +364,10 @@ __device__ __forceinline__ void dma_geom(int dw, int ii, int lane, int &row, int
     inp = (c % F::kChunksPerSlot) * F::kInputsPerChunk;
 }
 
-template <class F, int DPW>
-__device__ __forceinline__ void prod_item(Producer<DPW> &P, int dw, int lane) {
+template <class F, int DPW, class W>
+__device__ __forceinline__ void prod_item(Producer<DPW> &P, const uint2 *tab, int dw, int lane) {
     Task tk;
-    decode_task(P.it, tk);
+    task_of<W>(P.it, tab, tk);
     P.okmask = 0;
 #pragma unroll
     for (int ii = 0; ii < DPW; ++ii) {
@@ -343,11 +396,11 @@ __device__ __forceinline__ void prod_item(Producer<DPW> &P, int dw, int lane) {
 }
 
 template <class F, int DPW, class W>
-__device__ __forceinline__ void prod_advance(Producer<DPW> &P, const W &w, int total_flat, int grid,
-                                             int dw, int lane) {
+__device__ __forceinline__ void prod_advance(Producer<DPW> &P, const W &w, const uint2 *tab, int total_flat,
+                                             int grid, int dw, int lane) {
     P.valid = false;
     while (P.B < total_flat && !(P.valid = w.get(P.B, P.it))) P.B += grid;
-    if (P.valid) prod_item<F, DPW>(P, dw, lane);
+    if (P.valid) prod_item<F, DPW, W>(P, tab, dw, lane);
 }
 
 // Issue the next stage's DMA into ring slot issued % kRing.  Past the end of
@@ -355,7 +408,7 @@ __device__ __forceinline__ void prod_advance(Producer<DPW> &P, const W &w, int t
 // the slot just consumed), so that exactly kRing - 2 stages are always in
 // flight after the awaited one and every wait is the same constant.
 template <class F, int DPW, class W>
-__device__ __forceinline__ void prod_issue(Producer<DPW> &P, const W &w, int nt, int nst,
+__device__ __forceinline__ void prod_issue(Producer<DPW> &P, const W &w, const uint2 *tab, int nt, int nst,
                                            int total_flat, int grid, uint8_t *lds, uint32_t lds_base,
                                            int dw, int lane) {
     const unsigned slot = P.issued & (kRing - 1);
@@ -402,7 +455,7 @@ __device__ __forceinline__ void prod_issue(Producer<DPW> &P, const W &w, int nt,
     if (++P.ps == nst) {
         P.ps = 0;
         P.B += grid;
-        prod_advance<F, DPW>(P, w, total_flat, grid, dw, lane);
+        prod_advance<F, DPW>(P, w, tab, total_flat, grid, dw, lane);
     }
 }
 
@@ -457,6 +510,12 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     constexpr int DPW = dma_per_wave<kDmaWaves>();
     const int grid = gridDim.x;
     const int nst = (nt + F::kT - 1) / F::kT;
+    uint2 *tab = (uint2 *)(lds + kTaskTabOff);
+    if constexpr (W::kTable) {
+        w.fill_table(tab, tid, C::kThreads);
+        wait_lds();  // the table's LDS writes have landed
+        block_barrier();
+    }
 
     // ---- consumer cursor (drives the loop of every wave)
     int cB = blockIdx.x;
@@ -471,13 +530,13 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     P.ps = 0;
     P.issued = 0;
     P.zero = (const uint8_t *)&kZeroChunk;
-    if (dma_wave) prod_advance<F, DPW>(P, w, total_flat, grid, dw, lane);
+    if (dma_wave) prod_advance<F, DPW>(P, w, tab, total_flat, grid, dw, lane);
 
     WaveJob job;
     typename C::Bases fb;
     {
         Task tk;
-        decode_task(cit, tk);
+        task_of<W>(cit, tab, tk);
         job = C::job(tk, wave, cit.ninput);
         C::bind(job, lane, fb);
     }
@@ -494,10 +553,11 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     static_assert(kAhead + DPW < 64, "vmcnt range");
     if (dma_wave)
         for (int k = 0; k < kRing - 1; ++k)
-            prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+            prod_issue<F, DPW>(P, w, tab, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     if (dma_wave) wait_vm<kAhead>();
+    wait_lds();  // and any LDS stores of the synchronous (zero-fill) path
     block_barrier();
-    if (dma_wave) prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    if (dma_wave) prod_issue<F, DPW>(P, w, tab, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
     C::read(lds, fb, ra);
     wait_lds();
     C::prep(ra, pa);
@@ -519,7 +579,7 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
             while (cB < total_flat && !(more = w.get(cB, nit))) cB += grid;
             if (more) {
                 Task tk;
-                decode_task(nit, tk);
+                task_of<W>(nit, tab, tk);
                 njob = C::job(tk, wave, nit.ninput);
                 C::bind(njob, lane, nfb);
             }
@@ -533,7 +593,7 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
         C::head(pcur, cur, acc);
         __builtin_amdgcn_sched_barrier(0);
         if (more) {
-            if (dma_wave) prod_issue<F, DPW>(P, w, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+            if (dma_wave) prod_issue<F, DPW>(P, w, tab, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
             C::read(lds + ((s + 1) & (kRing - 1)) * kStageBytes, nfb, nxt);
         }
         __builtin_amdgcn_sched_barrier(0);

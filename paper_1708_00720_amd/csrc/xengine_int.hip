@@ -544,6 +544,8 @@ __global__ __launch_bounds__(IntKernelConsumer<CI4>::kThreads, 1) void xengine_i
 // negative entry pads the per-XCD queues to equal length).  The subarray
 // record gives the gulp's place in the arena and the channel's output.
 struct BatchArray {
+    static constexpr bool kTable = false;
+    __device__ __forceinline__ void fill_table(uint2 *, int, int) const {}
     const uint8_t *arena;
     uint8_t *out;
     const BatchUnit *units;
