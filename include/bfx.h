@@ -146,10 +146,13 @@ int64_t bfx_xengine_nacc(const bfx_xengine *plan);
  * every variant computes the same result (integer paths: the same bits):
  *   0, 1  the plan's own MFMA type (int8 for ci4/ci8, binary16 for cf16), with
  *         four or eight waves issuing the stage copies into LDS;
- *   2, 3  ci4 plans only (not batched): the same on FP8 MFMA -- every 4-bit
+ *   2, 3  ci4 plans (not batched): the same on FP8 MFMA -- every 4-bit
  *         value is exact in e4m3, products and sums are integers below 2^23
  *         and binary32 accumulates them exactly (Sec. 6: 4+4-bit voltages;
- *         Sec. 2.2: quantized types down to a few bits).
+ *         Sec. 2.2: quantized types down to a few bits);
+ *         cf16 plans: variants 0, 1 with each LDS stage read two stages
+ *         ahead (the same arithmetic in the same order; gulps of at most 16
+ *         samples run variant 0 or 1 instead).
  *
  * bfx_xengine_autotune times each variant on the plan's shape with `ntime`
  * samples (1 <= ntime <= min(bfx_xengine_max_ntime, 2^20)) on `stream` and

@@ -614,6 +614,157 @@ __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int 
     wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
 }
 
+// A work source that decodes every task in closed form (no LDS table).
+template <class W>
+struct ClosedForm : W {
+    static constexpr bool kTable = false;
+    __device__ explicit ClosedForm(const W &w) : W(w) {}
+};
+
+// Wait until at most N of this wave's LDS operations are in flight (vmcnt and
+// expcnt left at their maxima).
+template <int N>
+__device__ inline void wait_lgkm() {
+    static_assert(N >= 0 && N < 16, "lgkmcnt range");
+    __builtin_amdgcn_s_waitcnt(0xC07F | (N << 8));
+}
+
+// The same persistent loop with each stage's transposing reads issued two
+// stages ahead, for a consumer whose MFMA operands are the reads themselves
+// (C::Pre empty; C::kLdsReads LDS instructions per stage).  Iteration s: the
+// reads of stage s+1 are in flight; every wave waits for its reads of stage s
+// only, the DMA waves for their DMA of stage s+2, and the barrier publishes
+// stage s+2 and frees the slot of stage s.  The MFMAs of stage s then start,
+// the slot is refilled, and the reads of stage s+2 go out behind them, so a
+// stage's reads have two stages of MFMA work to return in.  Three register
+// sets rotate.  A read cursor runs two stages ahead of the MFMA work and
+// decodes each next item (in closed form: an LDS table read would wait for
+// the reads in flight); the MFMA side takes the item over at its last stage.
+// Items must have at least two stages (the host launches this loop only
+// then), so the read cursor is at most one item ahead.
+template <class F, class C, int DMA_WAVES, class W0>
+__device__ __forceinline__ void xe_loop_ra2(const W0 &w0, int nt, int total_flat, int overwrite) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t *)lds;
+    typedef ClosedForm<W0> W;
+    const W w(w0);
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+    const int lane = tid & 63;
+    constexpr int kDmaWaves = DMA_WAVES;
+    static_assert(C::kWaves % kDmaWaves == 0, "DMA waves spread over the SIMDs");
+    const bool dma_wave = wave < kDmaWaves;
+    const int dw = wave;
+    constexpr int DPW = dma_per_wave<kDmaWaves>();
+    const int grid = gridDim.x;
+    const int nst = (nt + F::kT - 1) / F::kT;
+    const uint2 *tab = nullptr;  // (closed-form decode)
+
+    // ---- the MFMA side's item
+    int cB = blockIdx.x;
+    Item cit;
+    bool cvalid = false;
+    while (cB < total_flat && !(cvalid = w.get(cB, cit))) cB += grid;
+    if (!cvalid) return;  // no work for this workgroup
+
+    // ---- producer cursor
+    Producer<DPW> P;
+    P.B = blockIdx.x;
+    P.ps = 0;
+    P.issued = 0;
+    P.zero = (const uint8_t *)&kZeroChunk;
+    if (dma_wave) prod_advance<F, DPW>(P, w, tab, total_flat, grid, dw, lane);
+
+    WaveJob job;
+    typename C::Bases rfb;  // bases of the stage the read cursor reads next
+    {
+        Task tk;
+        decode_task(cit, tk);
+        job = C::job(tk, wave, cit.ninput);
+        C::bind(job, lane, rfb);
+    }
+    // ---- read cursor: flat id, stage within its item; the item it moved on
+    // to last, for the MFMA side (pvalid: there is one)
+    int rB = cB, rcs = 0;
+    bool rvalid = true, pvalid = false;
+    WaveJob pjob = job;
+    Item pit = cit;
+    auto radvance = [&]() __attribute__((always_inline)) {
+        if (++rcs < nst) return;
+        rcs = 0;
+        rB += grid;
+        Item nit = cit;
+        bool v = false;
+        while (rB < total_flat && !(v = w.get(rB, nit))) rB += grid;
+        rvalid = v;
+        pvalid = v;
+        if (v) {
+            Task tk;
+            decode_task(nit, tk);
+            pjob = C::job(tk, wave, nit.ninput);
+            C::bind(pjob, lane, rfb);
+            pit = nit;
+        }
+    };
+
+    typename C::Acc acc;
+    C::zero(acc);
+    typename C::Raw ra = {}, rb = {}, rc = {};
+    typename C::Pre pre = {};
+
+    constexpr int kAhead2 = (kRing - 3) * DPW;  // DMA operations after the stage two ahead
+    if (dma_wave)
+        for (int k = 0; k < kRing - 1; ++k)
+            prod_issue<F, DPW>(P, w, tab, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    if (dma_wave) wait_vm<kAhead2>();  // stages 0 and 1 have landed
+    wait_lds();
+    block_barrier();
+    if (dma_wave) prod_issue<F, DPW>(P, w, tab, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+    C::read(lds, rfb, ra);
+    radvance();
+    C::read(lds + kStageBytes, rfb, rb);
+    radvance();
+
+    unsigned s = 0;  // stage whose MFMA work the next step does
+    int cs = 0;      // its index within the MFMA side's item
+    // One stage: MFMAs of stage s from cur; reads of stage s+2 into nxt.
+    // Returns whether a stage follows.
+    auto step = [&](typename C::Raw &cur, typename C::Raw &nxt) __attribute__((always_inline)) {
+        const bool last = cs + 1 == nst;
+        const bool more = !last || pvalid;
+        const bool rd = rvalid;  // stage s+2 exists
+        if (rd) {
+            // this wave's reads of stage s are back (those of stage s+1 may
+            // not be): its slot may be refilled once every wave is here
+            wait_lgkm<C::kLdsReads>();
+            if (dma_wave) wait_vm<kAhead2>();
+            block_barrier();
+        }
+        C::head(pre, cur, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (rd) {
+            if (dma_wave) prod_issue<F, DPW>(P, w, tab, nt, nst, total_flat, grid, lds, lds_base, dw, lane);
+            C::read(lds + ((s + 2) & (kRing - 1)) * kStageBytes, rfb, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        C::tail(pre, cur, nxt, pre, acc);
+        if (last) {
+            if (job.active) C::epilogue(job, cit, acc, lane, overwrite);
+            C::zero(acc);
+            job = pjob;
+            cit = pit;
+        }
+        cs = last ? 0 : cs + 1;
+        if (rd) radvance();
+        ++s;
+        return more;
+    };
+    while (step(ra, rc) && step(rb, ra) && step(rc, rb)) {
+    }
+    wait_vm<0>();  // no DMA may still target LDS when the workgroup retires
+}
+
 // Persistent grid: one workgroup per CU, a multiple of 8 (the XCD count) and
 // at most the number of flat ids.
 inline int64_t persistent_grid(int num_cus, int64_t total_flat) {

@@ -85,6 +85,7 @@ struct F16Consumer {
     struct Raw {
         v8h a[4], b[2];  // row and column fragments of one stage
     };
+    static constexpr int kLdsReads = 12;  // LDS instructions of one stage's reads (6 fragments x 2)
     struct Bases {
         int fb[6];  // 4 row fragments, 2 column fragments
     };
@@ -229,10 +230,20 @@ __global__ __launch_bounds__(F16Consumer::kThreads, 1) void xengine_f16_kernel(S
     xe_loop<F16Fmt, F16Consumer, DW>(w, nt, total_flat, overwrite);
 }
 
-// Kernel variants a plan chooses between (index = variant).
+// The same with each stage's reads issued two stages ahead (items of at least
+// two stages).
+template <int DW>
+__global__ __launch_bounds__(F16Consumer::kThreads, 1) void xengine_f16_ra2_kernel(SingleArray w, int nt,
+                                                                      int total_flat, int overwrite) {
+    xe_loop_ra2<F16Fmt, F16Consumer, DW>(w, nt, total_flat, overwrite);
+}
+
+// Kernel variants a plan chooses between (index = variant): four or eight
+// DMA waves, reads one (0, 1) or two (2, 3) stages ahead.
 typedef void (*F16Kernel)(SingleArray, int, int, int);
-constexpr int kF16Variants = 2;
-const F16Kernel kF16[kF16Variants] = {xengine_f16_kernel<4>, xengine_f16_kernel<8>};
+constexpr int kF16Variants = 4;
+const F16Kernel kF16[kF16Variants] = {xengine_f16_kernel<4>, xengine_f16_kernel<8>, xengine_f16_ra2_kernel<4>,
+                                      xengine_f16_ra2_kernel<8>};
 
 DeviceInit g_init;
 
@@ -268,6 +279,8 @@ hipError_t launch_xengine_f16(const void *in, int64_t nt, int32_t nchan, int32_t
     w.ngroups = (nchan + w.npk - 1) / w.npk;
     const int64_t total_flat = ((int64_t)w.ngroups + 7) / 8 * 8 * w.nitems;
     const int64_t grid = persistent_grid(num_cus, total_flat);
+    // reads two stages ahead need items of two stages at least
+    if (variant >= 2 && (nt + F16Fmt::kT - 1) / F16Fmt::kT < 2) variant -= 2;
     hipLaunchKernelGGL(kF16[variant], dim3((unsigned)grid), dim3(F16Consumer::kThreads), kLdsBytes, s, w,
                        (int)nt, (int)total_flat, m);
     return hipGetLastError();

@@ -621,7 +621,7 @@ int64_t xengine_items(int32_t ninput, int32_t nchan) {
 
 int xengine_num_variants(bfx_dtype in, bool batched) {
     if (batched) return kBatchedVariants;
-    return in == BFX_CI4 ? 4 : 2;
+    return in == BFX_CI4 || in == BFX_CF16 ? 4 : 2;
 }
 
 hipError_t launch_xengine_int(bool ci4, const void *in, int64_t nt, int32_t nchan, int32_t ninput,
