@@ -1,8 +1,9 @@
 """GPU: the X-engine kernel variants and the autotuner.  Every variant must
 give the same bits (integer paths) and the same binary32 values (the FP16
-path: the variants differ only in which waves issue the LDS copies, not in
-the arithmetic); the tuner keeps the plan's accumulation count, picks a
-valid variant and records it in the tune cache."""
+path: the variants differ only in which waves issue the LDS copies and how
+far ahead the LDS stages are read, not in the arithmetic); the tuner keeps
+the plan's accumulation count, picks a valid variant and records it in the
+tune cache."""
 import os
 
 import numpy as np
@@ -63,6 +64,39 @@ def test_f16_variants_identical():
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     plan.close()
+
+
+@pytest.mark.parametrize("T", [16, 17, 32, 48, 100])
+def test_f16_read_ahead_many_items(T):
+    """The FP16 variants that read two stages ahead hand each workgroup's
+    read cursor over from item to item about seven times here (600 channels
+    x 3 items of a 200-input array on at most 256 workgroups), with items of
+    2 (T = 17, 32), 3 and 7 stages, and T = 16 (one stage) runs variants 0
+    and 1 in their place: every variant gives the same values as variant 0,
+    and variant 0 equals the oracle on two channels within the binary32
+    summation bound."""
+    import paper_1708_00720_amd as bfx
+    F, N = 600, 200
+    banner(f"variants cf16 read-ahead T={T} F={F} N={N}")
+    x = synth.cf16_voltages(60 + T, T, F, N)
+    plan = bfx.bfx_xengine_create(N, F, "cf16")
+    nv = bfx.bfx_xengine_num_variants(plan)
+    assert nv == 4
+    outs = _acc_variants(plan, to_dev(x), T, nv)
+    for v, o in enumerate(outs[1:], 1):
+        assert np.array_equal(o, outs[0]), f"variant {v}"
+    plan.close()
+    chans = [0, F - 1]
+    xs = x[:, chans]
+    want = oracle.xengine_f64(xs[..., 0].astype(np.float64), xs[..., 1].astype(np.float64))
+    got = outs[0].astype(np.float64).reshape(F, N * (N + 1) // 2, 2)[chans]
+    # |dV_ij| <= gamma_{T+1} sqrt(V_ii V_jj) (binary16 products exact in binary32)
+    il, jl = np.tril_indices(N)
+    diag = want[:, il * (il + 1) // 2 + il, 0]                      # V_ii at each packed (i, j)
+    diagj = want[:, jl * (jl + 1) // 2 + jl, 0]
+    gamma = (T + 1) * 2.0 ** -24 / (1 - (T + 1) * 2.0 ** -24)
+    err = np.hypot(got[..., 0] - want[..., 0], got[..., 1] - want[..., 1])
+    assert np.all(err <= gamma * np.sqrt(diag * diagj))
 
 
 def test_batched_variants_bit_exact():
