@@ -486,11 +486,19 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
                           (int)__builtin_amdgcn_perm(b[3], b[2], 0x07050301u)};
         }
     };
+    // (every K step unguarded when the item has all kPKS of them: a
+    // branch per step would keep the compiler from overlapping them)
+    const bool full = nks == kPKS;
     auto read_frags = [&](const uint8_t *stage, v4i (&f)[kPKS]) __attribute__((always_inline)) {
         const uint8_t *row = stage + kPRow * R;
+        if (full) {
 #pragma unroll
-        for (int ks = 0; ks < kPKS; ++ks)
-            if (ks < nks) f[ks] = *(const v4i *)(row + 16 * ((4 * ks + q) ^ m));
+            for (int ks = 0; ks < kPKS; ++ks) f[ks] = *(const v4i *)(row + 16 * ((4 * ks + q) ^ m));
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < kPKS; ++ks)
+                if (ks < nks) f[ks] = *(const v4i *)(row + 16 * ((4 * ks + q) ^ m));
+        }
     };
 
     // Per-item constants of this lane's beam (bg*32 + 16 mt + m): its squared
@@ -557,16 +565,21 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
         // D[sample][beam] = X W^T over the stage's 16 samples: P1 = R Wre,
         // P2 = X' Wre, Q1 = R Wim, Q2 = X' Wim (R = 16 re, X' = 16 re + im + 8)
         v4i p1 = v4i{0, 0, 0, 0}, p2 = p1, q1 = p1, q2 = p1;
+        auto kstep = [&](int ks) __attribute__((always_inline)) {
+            v4i r, xo;
+            split_ci4_offset(cur[ks], r, xo);
+            p1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(r, wre[ks], p1, 0, 0, 0);
+            q2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(xo, wim[ks], q2, 0, 0, 0);
+            p2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(xo, wre[ks], p2, 0, 0, 0);
+            q1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(r, wim[ks], q1, 0, 0, 0);
+        };
+        if (full) {
 #pragma unroll
-        for (int ks = 0; ks < kPKS; ++ks) {
-            if (ks < nks) {
-                v4i r, xo;
-                split_ci4_offset(cur[ks], r, xo);
-                p1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(r, wre[ks], p1, 0, 0, 0);
-                q2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(xo, wim[ks], q2, 0, 0, 0);
-                p2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(xo, wre[ks], p2, 0, 0, 0);
-                q1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(r, wim[ks], q1, 0, 0, 0);
-            }
+            for (int ks = 0; ks < kPKS; ++ks) kstep(ks);
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < kPKS; ++ks)
+                if (ks < nks) kstep(ks);
         }
         __builtin_amdgcn_sched_barrier(0);
         // the next item's weights (in LDS since its stage kPWStage + kPSlots)
