@@ -384,26 +384,58 @@ __device__ __forceinline__ void pitem_next(PItem &c, int grid, int total, int nt
     pitem_first(c, c.B + grid, grid, total, ntb, nbg, nchan);
 }
 
-// This wave's share of stage k of item u: LDS row R = 2 (kPDma wave + j) +
-// lane / 32 holds time T0 + 256 (R >> 4) + 16 k + (R & 15) (clamped to the
-// last sample), its physical chunk lane % 32 the logical chunk
-// (lane % 32) ^ (R & 15); chunks past the row's inputs fetch chunk 0.
+// dma16 from a wave-uniform base plus a 32-bit per-lane offset (the
+// scalar-base form of the instruction): the base moves with the stage, the
+// offsets stay in registers for the whole launch.
+__device__ inline void dma16_at(const uint8_t *base, uint32_t off, uint32_t lds_wave_base) {
+    const uint64_t b = (uint64_t)(uintptr_t)base;
+    const uint64_t ub = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_wave_base)), "v"(off), "s"(ub)
+                 : "memory", "m0");
+}
+
+// This wave's share of a stage: LDS row R = 2 (kPDma wave + j) + lane / 32
+// (j < kPDma), all in the time quarter wave / 2, holds sample
+// T0 + 256 (R >> 4) + 16 k + (R & 15) of the item, its physical chunk
+// lane % 32 the logical chunk (lane % 32) ^ (R & 15); chunks past the row's
+// inputs fetch chunk 0.  The lane's byte offset of row R within the stage,
+// (R & 15) rstride + 16 chunk, is below 2^29 (rstride <= 65536 x 512).
+static_assert(16 % (2 * kPDma) == 0, "a wave's DMA rows lie in one 16-row group");
+__device__ __forceinline__ uint32_t pstage_off(int64_t rstride, int ninput, int wave, int lane, int j) {
+    const int R = 2 * (kPDma * wave + j) + (lane >> 5);
+    const int c = (lane & 31) ^ (R & 15);
+    const int cc = c < (ninput >> 4) ? c : 0;
+    return (uint32_t)((R & 15) * rstride + 16 * cc);
+}
+
+// Stage k of item u.  Rows past the last sample (only in an item that ends
+// early) are clamped to it.
 __device__ __forceinline__ void pstage_dma(const uint8_t *x, int64_t rstride, int ninput, int ntime,
-                                           const PItem &it, int k, uint32_t lds_stage, int wave, int lane) {
+                                           const PItem &it, int k, const uint32_t (&doff)[kPDma],
+                                           uint32_t lds_stage, int wave, int lane) {
     if (!it.valid) {
 #pragma unroll
         for (int j = 0; j < kPDma; ++j) dma16(&kZero16, lds_stage + 1024 * (kPDma * wave + j));
         return;
     }
-    const int64_t T0 = (int64_t)it.u.tb * kPItemT;
     const uint8_t *xf = x + (int64_t)it.u.f * ninput;
+    const int t16 = it.u.tb * kPItemT + 256 * ((2 * kPDma * wave) >> 4) + 16 * k;  // the rows' first sample
+    if (t16 + 16 <= ntime) {
+        const uint8_t *base = xf + (int64_t)t16 * rstride;
+#pragma unroll
+        for (int j = 0; j < kPDma; ++j) dma16_at(base, doff[j], lds_stage + 1024 * (kPDma * wave + j));
+        return;
+    }
     const int nck = ninput >> 4;
 #pragma unroll
     for (int j = 0; j < kPDma; ++j) {
         const int R = 2 * (kPDma * wave + j) + (lane >> 5);
         const int c = (lane & 31) ^ (R & 15);
         const int cc = c < nck ? c : 0;
-        const int64_t t = min(T0 + 256 * (R >> 4) + 16 * k + (R & 15), (int64_t)ntime - 1);
+        const int64_t t = min(t16 + (R & 15), ntime - 1);
         dma16(xf + t * rstride + 16 * cc, lds_stage + 1024 * (kPDma * wave + j));
     }
 }
@@ -443,6 +475,9 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
     const int64_t rstride = (int64_t)nchan * ninput;
     const int nks = ninput >> 6;
     const int R = 16 * qw + m;    // LDS row of this lane's B fragments
+    uint32_t doff[kPDma];         // this lane's DMA offsets within a stage
+#pragma unroll
+    for (int j = 0; j < kPDma; ++j) doff[j] = pstage_off(rstride, ninput, wave, lane, j);
 
     PItem cit;  // consumer's item
     pitem_first(cit, blockIdx.x, grid, total, ntb, nbg, nchan);
@@ -451,7 +486,7 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
     int pk = 0;       // producer's stage within pit
 
     auto produce = [&](uint32_t slot_base) __attribute__((always_inline)) {
-        pstage_dma(x, rstride, ninput, ntime, pit, pk, slot_base, wave, lane);
+        pstage_dma(x, rstride, ninput, ntime, pit, pk, doff, slot_base, wave, lane);
         if (pit.valid && ++pk == kPStages) {
             pk = 0;
             pitem_next(pit, grid, total, ntb, nbg, nchan);
@@ -504,11 +539,16 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
     // Per-item constants of this lane's beam (bg*32 + 16 mt + m): its squared
     // scale, and 8 x the sums of its weights' real and imaginary parts over
     // all inputs (the offset that X' carries into P2 and Q2).
+    const int nwin = ntime >> LOGNAVG;
     double sb2 = 0.0;
-    int c8re = 0, c8im = 0;
+    int c8im = 0, m8re = 0;  // 8 S_im and -8 S_re
+    float *ob = out;         // the beam's row of windows in this item's channel
+    bool bok = false;        // the lane's beam exists
     auto item_consts = [&]() __attribute__((always_inline)) {
         const int beam = cit.u.bg * kBeams + 16 * mt + m;
-        const double sb = (double)(beam < nbeam ? scale[beam] : 0.0f);
+        bok = beam < nbeam;
+        ob = out + ((int64_t)beam * nchan + cit.u.f) * nwin;
+        const double sb = (double)(bok ? scale[beam] : 0.0f);
         sb2 = sb * sb;
         int sre = 0, sim = 0;
 #pragma unroll
@@ -523,7 +563,7 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
         sim += swz_xor<16>(sim);
         sre += xor32(sre, lane);
         sim += xor32(sim, lane);
-        c8re = 8 * sre;
+        m8re = -8 * sre;
         c8im = 8 * sim;
     };
 
@@ -535,7 +575,6 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
     read_frags(lds, fa);
 
     constexpr int kTilesPerWin = LOGNAVG > 4 ? 1 << (LOGNAVG - 4) : 1;
-    const int nwin = ntime >> LOGNAVG;
     double part = 0.0;
     PItem cnext = cit;  // the consumer's next item
     pitem_next(cnext, grid, total, ntb, nbg, nchan);
@@ -588,38 +627,45 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
         // T0 + 256 qw + 16 ck + 4q + v (v = 0..3), so windows of up to 4
         // samples are lane-local, 8 and 16 add the lanes 16 and 32 away, 32
         // and 64 add consecutive stages.
-        const int64_t t0 = (int64_t)cit.u.tb * kPItemT + 256 * qw + 16 * ck + 4 * q;
-        const int beam = cit.u.bg * kBeams + 16 * mt + m;
-        const bool bok = beam < nbeam;
+        const int tw = cit.u.tb * kPItemT + 256 * qw + 16 * ck;  // the wave's first sample
+        const int t0 = tw + 4 * q;
         // |y|^2 in binary64: with at most 512 inputs |Re y|, |Im y| < 2^20, so
         // every sample's power is an integer below 2^41 and a window's sum
         // (up to 64 samples) one below 2^47, exact in binary64 whatever the
         // order of the additions.
-        double e[4];
+        double dr[4], di[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int yr = (p1[v] >> 4) - q2[v] + q1[v] + c8im;
-            const int yi = (q1[v] >> 4) + p2[v] - p1[v] - c8re;
-            const double dr = (double)yr, di = (double)yi;
-            e[v] = __builtin_fma(dr, dr, di * di);
+            dr[v] = (double)((p1[v] >> 4) + (q1[v] - q2[v]) + c8im);
+            di[v] = (double)((q1[v] >> 4) + (p2[v] - p1[v]) + m8re);
         }
-        float *ob = out + ((int64_t)beam * nchan + cit.u.f) * nwin;
         if constexpr (LOGNAVG == 0) {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (bok && t0 + v < nwin) ob[t0 + v] = (float)(sb2 * e[v]);
+                if (bok && t0 + v < nwin) ob[t0 + v] = (float)(sb2 * __builtin_fma(dr[v], dr[v], di[v] * di[v]));
         } else if constexpr (LOGNAVG == 1) {
-            const int64_t u0 = t0 >> 1;
-            if (bok && u0 < nwin) ob[u0] = (float)(sb2 * (e[0] + e[1]));
-            if (bok && u0 + 1 < nwin) ob[u0 + 1] = (float)(sb2 * (e[2] + e[3]));
+            const int u0 = t0 >> 1;
+            double e[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int a = 2 * h, b = 2 * h + 1;
+                e[h] = __builtin_fma(dr[a], dr[a], di[a] * di[a]);
+                e[h] = __builtin_fma(dr[b], dr[b], __builtin_fma(di[b], di[b], e[h]));
+            }
+            if (bok && u0 < nwin) ob[u0] = (float)(sb2 * e[0]);
+            if (bok && u0 + 1 < nwin) ob[u0 + 1] = (float)(sb2 * e[1]);
         } else {
-            double sum = (e[0] + e[1]) + (e[2] + e[3]);
+            double sum = di[0] * di[0];
+            sum = __builtin_fma(dr[0], dr[0], sum);
+#pragma unroll
+            for (int v = 1; v < 4; ++v) sum = __builtin_fma(dr[v], dr[v], __builtin_fma(di[v], di[v], sum));
             if constexpr (LOGNAVG >= 3) sum += swz_xor_f64<16>(sum);
             if constexpr (LOGNAVG >= 4) sum += xor32_f64(sum, lane);
             part += sum;
             constexpr int kLeadMask = LOGNAVG >= 4 ? 3 : LOGNAVG == 3 ? 1 : 0;
             if ((ck % kTilesPerWin) == kTilesPerWin - 1) {
-                const int64_t u = t0 >> LOGNAVG;
+                // a window starts at this wave's sample tw (16 | tw) from 16 samples on
+                const int u = (LOGNAVG >= 4 ? tw : t0) >> LOGNAVG;
                 if ((q & kLeadMask) == 0 && bok && u < nwin) ob[u] = (float)(sb2 * part);
                 part = 0.0;
             }
