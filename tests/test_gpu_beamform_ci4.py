@@ -36,6 +36,8 @@ def _run(x, w, scale, N, F, B, T, navg):
     (64, 1, 1, 16, 16), (64, 3, 5, 48, 1), (128, 2, 32, 256, 2), (192, 5, 33, 320, 4),
     (320, 3, 40, 512, 8), (512, 9, 64, 272, 16), (256, 4, 7, 640, 32), (448, 2, 16, 768, 64),
     (576, 3, 17, 272, 16), (1024, 2, 33, 512, 64),
+    # a stage that ends inside the data (ntime not a multiple of 16)
+    (64, 2, 3, 37, 1), (256, 3, 9, 1000, 8),
 ])
 def test_extreme_codes_ragged(N, F, B, T, navg):
     banner(f"beamform_ci4 extremes N={N} F={F} B={B} T={T} navg={navg}")
