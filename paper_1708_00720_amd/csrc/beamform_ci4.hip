@@ -576,6 +576,9 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
 
     constexpr int kTilesPerWin = LOGNAVG > 4 ? 1 << (LOGNAVG - 4) : 1;
     double part = 0.0;
+    float kw[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // a lane's windows of the item (navg 16)
+    // every beam row of windows starts 16-byte aligned
+    const bool row16 = (nwin & 3) == 0 && ((uintptr_t)out & 15) == 0;
     PItem cnext = cit;  // the consumer's next item
     pitem_next(cnext, grid, total, ntb, nbg, nchan);
     int ck = 0;         // consumer's stage within cit
@@ -663,7 +666,31 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
             if constexpr (LOGNAVG >= 4) sum += xor32_f64(sum, lane);
             part += sum;
             constexpr int kLeadMask = LOGNAVG >= 4 ? 3 : LOGNAVG == 3 ? 1 : 0;
-            if ((ck % kTilesPerWin) == kTilesPerWin - 1) {
+            if constexpr (LOGNAVG == 4) {
+                // One window per stage and beam, its sum in every lane of the
+                // beam.  Lane (q, m) shifts in the windows of stages 4q .. 4q+3
+                // and stores those four consecutive windows at the item's last
+                // stage: one 16-byte store per lane and item instead of a
+                // 4-byte store per stage to 16 beam rows.
+                const float pw = (float)(sb2 * part);
+                part = 0.0;
+                if (ck < 4 * q + 4) {
+                    kw[0] = kw[1];
+                    kw[1] = kw[2];
+                    kw[2] = kw[3];
+                    kw[3] = pw;
+                }
+                if (last && bok) {
+                    const int u = ((cit.u.tb * kPItemT + 256 * qw) >> 4) + 4 * q;
+                    if (row16 && u + 4 <= nwin) {
+                        *(float4 *)(ob + u) = make_float4(kw[0], kw[1], kw[2], kw[3]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (u + v < nwin) ob[u + v] = kw[v];
+                    }
+                }
+            } else if ((ck % kTilesPerWin) == kTilesPerWin - 1) {
                 // a window starts at this wave's sample tw (16 | tw) from 16 samples on
                 const int u = (LOGNAVG >= 4 ? tw : t0) >> LOGNAVG;
                 if ((q & kLeadMask) == 0 && bok && u < nwin) ob[u] = (float)(sb2 * part);

@@ -22,10 +22,13 @@ from gpu_util import banner, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _run(x, w, scale, N, F, B, T, navg):
+def _run(x, w, scale, N, F, B, T, navg, out_offset=0):
+    """Run the library; the output starts out_offset floats into its buffer."""
     import torch
     import paper_1708_00720_amd as bfx
-    out = torch.full((B * F * (T // navg),), float("nan"), dtype=torch.float32, device="cuda")
+    n = B * F * (T // navg)
+    buf = torch.full((n + out_offset,), float("nan"), dtype=torch.float32, device="cuda")
+    out = buf[out_offset:]
     bfx.bfx_beamform_ci4(to_dev(x), to_dev(w), torch.from_numpy(np.asarray(scale, np.float32)).cuda(),
                          N, F, B, T, navg, out)
     torch.cuda.synchronize()
@@ -93,3 +96,21 @@ def test_many_items_ragged():
     for f in (0, 1, 7, 8, 255, 256, 263, 511, 512, 519):
         want = oracle.beamform_ci4(np.ascontiguousarray(x[:, f:f + 1]), w[f:f + 1], scale, navg)
         assert np.array_equal(got[:, f:f + 1].view(np.uint32), want.view(np.uint32)), f
+
+
+@pytest.mark.parametrize("out_offset", [0, 1])
+def test_navg16_window_rows(out_offset):
+    """navg 16, where a lane gathers four consecutive windows of its beam and
+    stores them once per 1024-sample item: 1088 samples (a second item of 64
+    samples, so only the first four windows of its first time quarter exist),
+    68 windows per row, 40 beams (a partial beam group).  With the output
+    16-byte aligned whole rows of four windows are stored at once; one float
+    further on, window by window.  Every channel bit-exact."""
+    N, F, B, T, navg = 256, 5, 40, 1088, 16
+    banner(f"beamform_ci4 navg16 rows N={N} F={F} B={B} T={T} out_offset={out_offset}")
+    x = synth.extreme_voltages(41, T, F, N, "ci4")
+    w = synth.extreme_int8_weights(42, F, B, N)
+    scale = np.random.default_rng(43).uniform(0.001, 3.0, B).astype(np.float32)
+    got = _run(x, w, scale, N, F, B, T, navg, out_offset)
+    want = oracle.beamform_ci4(x, w, scale, navg)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
