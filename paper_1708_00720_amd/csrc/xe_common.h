@@ -488,13 +488,14 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // next item's job is decoded first, so its first stage is read under the same
 // overlap.  The loop body runs twice per trip with the two register sets
 // swapped, so no operand is copied.
-// The vector-memory counter also counts the epilogue's stores, which may
-// complete out of order with the loads; the DMA loads themselves complete in
-// order.  A wait for "at most N outstanding", N = the DMA loads issued after
-// the awaited stage, is therefore exact for the loads whatever the stores do:
-// while the awaited DMA is outstanding so is every later load, so at least
-// N + 1 operations are.  Pending stores can only lengthen the wait, and
-// waves that issue no DMA do not wait on the counter at all.
+// The vector-memory counter also counts the epilogue's stores, and it counts
+// down in issue order (the compiler's own waits rely on that).  A wait for
+// "at most N outstanding", N = the DMA loads issued after the awaited stage,
+// is therefore safe whatever the stores do: while the awaited DMA is
+// outstanding so is every later load, so at least N + 1 operations are.
+// Stores issued after the awaited stage lengthen the wait; counting them in
+// as well was timed and gained nothing, so the wait stays a constant.  Waves
+// that issue no DMA do not wait on the counter at all.
 template <class F, class C, int DMA_WAVES, class W>
 __device__ __forceinline__ void xe_loop(const W &w, int nt, int total_flat, int overwrite) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
