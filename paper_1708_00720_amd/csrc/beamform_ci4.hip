@@ -334,7 +334,9 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
 // v_mfma_i32_16x16x64_i8 have the same lane layout on both sides), so a lane
 // holds four consecutive samples of one beam: windows of up to 4 samples are
 // lane-local, 8 and 16 add the lanes 16 and 32 away, 32 and 64 add
-// consecutive stages.  The nibble split takes two operations per word
+// consecutive stages.  At 16 samples a window a lane gathers its beam's
+// windows of four consecutive stages in registers and stores them once per
+// item, 16 bytes at a time.  The nibble split takes two operations per word
 // instead of three: R = 16 re (mask) and X' = 16 re + im + 8 (flip bit 3),
 //   P1 = R Wre, P2 = X' Wre, Q1 = R Wim, Q2 = X' Wim,
 //   Re y = P1/16 - (Q2 - Q1 - 8 S_im),  Im y = Q1/16 + (P2 - P1 - 8 S_re),
