@@ -84,6 +84,7 @@ def test_beamform_navg(navg):
     (1056, 1, 70, 272, 8),   # five K chunks, three beam groups, a 256-sample unit + a 16-sample tail
     (512, 9, 32, 512, 16),   # channel count not a multiple of 8
     (256, 2, 16, 600, 8),    # two full 256-sample units + an 88-sample tail
+    (128, 3, 7, 336, 16),    # a full unit + 5 windows of the next; an odd beam count
 ])
 def test_beamform_ragged(N, F, B, T, navg):
     banner(f"beamform ragged N={N} F={F} B={B} T={T} navg={navg}")
