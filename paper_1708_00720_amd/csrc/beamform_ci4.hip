@@ -349,9 +349,9 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
 // v_mfma_i32_16x16x64_i8 have the same lane layout on both sides), so a lane
 // holds four consecutive samples of one beam: windows of up to 4 samples are
 // lane-local, 8 and 16 add the lanes 16 and 32 away, 32 and 64 add
-// consecutive stages.  At 16 samples a window a lane gathers its beam's
-// windows of four consecutive stages in registers and stores them once per
-// item, 16 bytes at a time.  The nibble split takes two operations per word
+// consecutive stages.  From 16 samples a window on, a lane gathers its beam's
+// windows of consecutive stages in registers and stores them once per item
+// (4, 2 or 1 windows).  The nibble split takes two operations per word
 // instead of three: R = 16 re (mask) and X' = 16 re + im + 8 (flip bit 3),
 //   P1 = R Wre, P2 = X' Wre, Q1 = R Wim, Q2 = X' Wim,
 //   Re y = P1/16 - (Q2 - Q1 - 8 S_im),  Im y = Q1/16 + (P2 - P1 - 8 S_re),
@@ -593,9 +593,10 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
 
     constexpr int kTilesPerWin = LOGNAVG > 4 ? 1 << (LOGNAVG - 4) : 1;
     double part = 0.0;
-    float kw[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // a lane's windows of the item (navg 16)
-    // every beam row of windows starts 16-byte aligned
+    float kw[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // a lane's windows of the item (navg >= 16)
+    // every beam row of windows starts 16-byte (8-byte) aligned
     const bool row16 = (nwin & 3) == 0 && ((uintptr_t)out & 15) == 0;
+    const bool row8 = (nwin & 1) == 0 && ((uintptr_t)out & 7) == 0;
     PItem cnext = cit;  // the consumer's next item
     pitem_next(cnext, grid, total, ntb, nbg, nchan);
     int ck = 0;         // consumer's stage within cit
@@ -683,33 +684,38 @@ __global__ __launch_bounds__(kPThreads, 1) void beamform_ci4_persistent_kernel(
             if constexpr (LOGNAVG >= 4) sum += xor32_f64(sum, lane);
             part += sum;
             constexpr int kLeadMask = LOGNAVG >= 4 ? 3 : LOGNAVG == 3 ? 1 : 0;
-            if constexpr (LOGNAVG == 4) {
-                // One window per stage and beam, its sum in every lane of the
-                // beam.  Lane (q, m) shifts in the windows of stages 4q .. 4q+3
-                // and stores those four consecutive windows at the item's last
-                // stage: one 16-byte store per lane and item instead of a
-                // 4-byte store per stage to 16 beam rows.
-                const float pw = (float)(sb2 * part);
-                part = 0.0;
-                if (ck < 4 * q + 4) {
-                    kw[0] = kw[1];
-                    kw[1] = kw[2];
-                    kw[2] = kw[3];
-                    kw[3] = pw;
+            if constexpr (LOGNAVG >= 4) {
+                // Windows of 16 samples and more: one per kTilesPerWin stages
+                // and beam, its sum in every lane of the beam.  Lane (q, m)
+                // shifts in the kW consecutive windows kW q .. kW q + kW - 1 of
+                // the wave's quarter and stores them at the item's last stage:
+                // one store of 4 kW bytes per lane and item instead of a 4-byte
+                // store per window to 16 beam rows.
+                constexpr int kW = 4 / kTilesPerWin;  // windows per lane and item: 4, 2, 1
+                if ((ck % kTilesPerWin) == kTilesPerWin - 1) {
+                    const float pw = (float)(sb2 * part);
+                    part = 0.0;
+                    if (ck / kTilesPerWin < kW * (q + 1)) {
+#pragma unroll
+                        for (int k = 0; k + 1 < kW; ++k) kw[k] = kw[k + 1];
+                        kw[kW - 1] = pw;
+                    }
                 }
                 if (last && bok) {
-                    const int u = ((cit.u.tb * kPItemT + 256 * qw) >> 4) + 4 * q;
-                    if (row16 && u + 4 <= nwin) {
+                    const int u = ((cit.u.tb * kPItemT + 256 * qw) >> LOGNAVG) + kW * q;
+                    if (kW == 4 && row16 && u + 4 <= nwin) {
                         *(float4 *)(ob + u) = make_float4(kw[0], kw[1], kw[2], kw[3]);
+                    } else if (kW == 2 && row8 && u + 2 <= nwin) {
+                        *(float2 *)(ob + u) = make_float2(kw[0], kw[1]);
                     } else {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v)
+                        for (int v = 0; v < kW; ++v)
                             if (u + v < nwin) ob[u + v] = kw[v];
                     }
                 }
-            } else if ((ck % kTilesPerWin) == kTilesPerWin - 1) {
-                // a window starts at this wave's sample tw (16 | tw) from 16 samples on
-                const int u = (LOGNAVG >= 4 ? tw : t0) >> LOGNAVG;
+            } else {
+                // a window ends in this stage
+                const int u = t0 >> LOGNAVG;
                 if ((q & kLeadMask) == 0 && bok && u < nwin) ob[u] = (float)(sb2 * part);
                 part = 0.0;
             }

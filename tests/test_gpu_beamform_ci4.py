@@ -100,16 +100,17 @@ def test_many_items_ragged():
         assert np.array_equal(got[:, f:f + 1].view(np.uint32), want.view(np.uint32)), f
 
 
+@pytest.mark.parametrize("navg", [16, 32, 64])
 @pytest.mark.parametrize("out_offset", [0, 1])
-def test_navg16_window_rows(out_offset):
-    """navg 16, where a lane gathers four consecutive windows of its beam and
-    stores them once per 1024-sample item: 1088 samples (a second item of 64
-    samples, so only the first four windows of its first time quarter exist),
-    68 windows per row, 40 beams (a partial beam group).  With the output
-    16-byte aligned whole rows of four windows are stored at once; one float
-    further on, window by window.  Every channel bit-exact."""
-    N, F, B, T, navg = 256, 5, 40, 1088, 16
-    banner(f"beamform_ci4 navg16 rows N={N} F={F} B={B} T={T} out_offset={out_offset}")
+def test_window_rows(navg, out_offset):
+    """navg 16 to 64, where a lane gathers 4, 2 or 1 consecutive windows of its
+    beam and stores them once per 1024-sample item: 1088 samples (a second
+    item of 64 samples, so only the first windows of its first time quarter
+    exist), 68, 34 or 17 windows per row, 40 beams (a partial beam group).
+    With the output 16- or 8-byte aligned a lane's windows leave at once; one
+    float further on, window by window.  Every channel bit-exact."""
+    N, F, B, T = 256, 5, 40, 1088
+    banner(f"beamform_ci4 window rows N={N} F={F} B={B} T={T} navg={navg} out_offset={out_offset}")
     x = synth.extreme_voltages(41, T, F, N, "ci4")
     w = synth.extreme_int8_weights(42, F, B, N)
     scale = np.random.default_rng(43).uniform(0.001, 3.0, B).astype(np.float32)
