@@ -233,9 +233,10 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
     // 0, 1) and 8*wave + 2g + 1 (registers 2, 3)
     const int nwin = ntime >> LOGNAVG;
     const int bw = u.bg * kBeams + 8 * wave + 2 * g;
-    // navg 16: window st of the unit is summed in all 16 lanes of a group;
-    // lane m keeps window m, and the unit's windows leave as one store per
-    // beam pair (16 consecutive windows of each beam) instead of one per tile
+    // navg 16 and 32: each window of the unit is summed in all 16 lanes of a
+    // group; lane m keeps window m, and the unit's windows leave as one store
+    // per beam pair (16 or 8 consecutive windows of each beam) instead of one
+    // per window
     float w0 = 0.0f, w1 = 0.0f;
 #pragma unroll
     for (int st = 0; st < kNT; ++st) {
@@ -249,8 +250,8 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
         constexpr int L = LOGNAVG < 4 ? LOGNAVG : 4;
         p0 = group_sum<L>(p0);
         p1 = group_sum<L>(p1);
-        if constexpr (LOGNAVG == 4) {
-            if (m == st) {
+        if constexpr (LOGNAVG >= 4) {
+            if (m == (st >> (LOGNAVG - 4))) {
                 w0 = p0;
                 w1 = p1;
             }
@@ -263,10 +264,11 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_kernel(
             }
         }
     }
-    if constexpr (LOGNAVG == 4) {
-        static_assert(kNT == 16, "one window per tile and lane of a 16-lane group");
-        const int uwin = (tu >> 4) + m;
-        if (uwin < nwin) {
+    if constexpr (LOGNAVG >= 4) {
+        static_assert(kNT == 16, "at most one window per lane of a 16-lane group");
+        constexpr int kW = kNT >> (LOGNAVG - 4);  // windows per unit: 16 or 8
+        const int uwin = (tu >> LOGNAVG) + m;
+        if (m < kW && uwin < nwin) {
             if (bw < nbeam) out[((int64_t)bw * nchan + u.f) * nwin + uwin] = w0;
             if (bw + 1 < nbeam) out[((int64_t)(bw + 1) * nchan + u.f) * nwin + uwin] = w1;
         }
