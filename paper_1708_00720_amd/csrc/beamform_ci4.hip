@@ -290,10 +290,12 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
     const int nwin = ntime >> LOGNAVG;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-        // navg 16: window s0 of beam 16 mt + 4q + v is summed in all 16 lanes
-        // of group q; lane m = 4v + s0 keeps it, so the group's windows leave
-        // as one store with every lane active (four consecutive windows of
-        // each of its four beams) instead of 16 stores with one lane in 16
+        // navg >= 16: window w of beam 16 mt + 4q + v is summed in all 16
+        // lanes of group q; lane m = kW v + w keeps it (kW = 4, 2, 1 windows per
+        // beam), so the group's windows leave as one store with 4 kW lanes
+        // active (kW consecutive windows of each of its four beams) instead of
+        // one store per window with one lane in 16
+        constexpr int kW = kTiles / kTilesPerWin;
         float keep = 0.0f;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -310,8 +312,8 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
                     acc += (int64_t)yr * yr + (int64_t)yi * yi;
                 }
                 acc = group_sum64<L>(acc);
-                if constexpr (LOGNAVG == 4) {
-                    if (m == 4 * v + s0) keep = (float)(sb2 * (double)acc);
+                if constexpr (LOGNAVG >= 4) {
+                    if (m == kW * v + s0 / kTilesPerWin) keep = (float)(sb2 * (double)acc);
                 } else {
                     const int t = tu + 64 * wave + 16 * s0 + m;
                     const int uwin = t >> LOGNAVG;
@@ -320,11 +322,12 @@ __global__ __launch_bounds__(kThreads, 2) void beamform_ci4_kernel(
                 }
             }
         }
-        if constexpr (LOGNAVG == 4) {
-            static_assert(kTiles == 4, "four windows per beam and wave");
-            const int beam = u.bg * kBeams + 16 * mt + 4 * q + (m >> 2);
-            const int uwin = ((tu + 64 * wave) >> 4) + (m & 3);
-            if (uwin < nwin && beam < nbeam) out[((int64_t)beam * nchan + u.f) * nwin + uwin] = keep;
+        if constexpr (LOGNAVG >= 4) {
+            static_assert(kTiles == 4, "at most four windows per beam and wave");
+            const int beam = u.bg * kBeams + 16 * mt + 4 * q + m / kW;
+            const int uwin = ((tu + 64 * wave) >> LOGNAVG) + m % kW;
+            if (m < 4 * kW && uwin < nwin && beam < nbeam)
+                out[((int64_t)beam * nchan + u.f) * nwin + uwin] = keep;
         }
     }
 }

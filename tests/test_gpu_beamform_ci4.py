@@ -41,8 +41,8 @@ def _run(x, w, scale, N, F, B, T, navg, out_offset=0):
     (576, 3, 17, 272, 16), (1024, 2, 33, 512, 64),
     # a stage that ends inside the data (ntime not a multiple of 16)
     (64, 2, 3, 37, 1), (256, 3, 9, 1000, 8),
-    # above 512 inputs at navg 16: a full 256-sample unit and one of 9 windows, 37 beams
-    (704, 3, 37, 400, 16),
+    # above 512 inputs at navg 16 and 32: a full 256-sample unit and a partial one, 37 beams
+    (704, 3, 37, 400, 16), (576, 2, 9, 320, 32),
 ])
 def test_extreme_codes_ragged(N, F, B, T, navg):
     banner(f"beamform_ci4 extremes N={N} F={F} B={B} T={T} navg={navg}")
