@@ -1,8 +1,8 @@
 // Dump of an integration (the paper's accumulate block, Sec. 4.1): copy the
 // visibility buffer out and/or fold it into a binary64 running sum,
-// run64[k] += (double)acc[k].  Memory-bound elementwise pass: 16-byte loads
-// of the accumulator, 2 x 16-byte read-modify-write of the running sum per
-// thread.  One group of four elements per thread: a grid that covers the
+// run64[k] += (double)acc[k].  Memory-bound elementwise pass: 16-byte
+// non-temporal loads of the accumulator, 2 x 16-byte read-modify-write of the
+// running sum per thread.  One group of four elements per thread: a grid that covers the
 // buffer keeps more loads in flight than a capped grid-stride loop (5.4 vs
 // 5.0 TB/s on 2048 x 131,328 cf32); the loop only strides beyond 2^23
 // workgroups.
@@ -14,6 +14,8 @@
 namespace bfx {
 namespace {
 
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+
 template <bool IS_INT>
 __global__ __launch_bounds__(256) void dump_kernel(const void *__restrict__ acc,
                                                    void *__restrict__ out,
@@ -21,7 +23,10 @@ __global__ __launch_bounds__(256) void dump_kernel(const void *__restrict__ acc,
     const int64_t n4 = n / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += stride) {
-        const int4 raw = ((const int4 *)acc)[k];
+        // the accumulator is read once: a non-temporal load keeps it from
+        // displacing the running sum's lines, which are read and written back
+        const v4i32 rv = __builtin_nontemporal_load((const v4i32 *)acc + k);
+        const int4 raw = make_int4(rv.x, rv.y, rv.z, rv.w);
         if (out) ((int4 *)out)[k] = raw;
         if (run64) {
             double v0, v1, v2, v3;
